@@ -1,0 +1,421 @@
+/*
+ * FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Written from the definitions of arXiv:1611.00075: the pair-force loop with
+ * Newton's third law (Sec. 2.2), the embedded-atom energy (Eqs. 1 and 2) and
+ * its three-step evaluation (Sec. 3.1), velocity-Verlet dynamics with a
+ * Verlet list whose cutoff exceeds the potential cutoff and the
+ * displacement rebuild rule (Sec. 3.3).  Nothing here is blocked, fused or
+ * reordered for speed.
+ *
+ * Compile with -ffp-contract=off: cell and neighbour decisions are compared
+ * bit for bit with the GPU library.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* periodic geometry                                                   */
+/* ------------------------------------------------------------------ */
+
+static double wrap1(double x, double L)
+{
+    double w = x - L * floor(x / L);
+    if (w >= L) w -= L;
+    if (w < 0.0) w += L;
+    return w;
+}
+
+void or_wrap(int64_t n, const double L[3], double *x, double *y, double *z)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] = wrap1(x[i], L[0]);
+        y[i] = wrap1(y[i], L[1]);
+        z[i] = wrap1(z[i], L[2]);
+    }
+}
+
+static int32_t cell1(double w, double inv_cell, int32_t nc)
+{
+    int32_t c = (int32_t)(w * inv_cell);
+    if (c >= nc) c = nc - 1;
+    if (c < 0) c = 0;
+    return c;
+}
+
+void or_cell_coords(int64_t n, const double L[3], const int32_t nc[3],
+                    const double *x, const double *y, const double *z,
+                    int32_t *cx, int32_t *cy, int32_t *cz)
+{
+    double inv[3];
+    for (int a = 0; a < 3; ++a) inv[a] = (double)nc[a] / L[a];
+    for (int64_t i = 0; i < n; ++i) {
+        cx[i] = cell1(x[i], inv[0], nc[0]);
+        cy[i] = cell1(y[i], inv[1], nc[1]);
+        cz[i] = cell1(z[i], inv[2], nc[2]);
+    }
+}
+
+double or_minimg(double a, double b, double L)
+{
+    double d = b - a;
+    if (d > 0.5 * L)
+        d -= L;
+    else if (d < -0.5 * L)
+        d += L;
+    return d;
+}
+
+/* squared minimum-image distance, summed left to right */
+static double dist2(const double L[3], const double *x, const double *y,
+                    const double *z, int64_t i, int64_t j, double d[3])
+{
+    d[0] = or_minimg(x[i], x[j], L[0]);
+    d[1] = or_minimg(y[i], y[j], L[1]);
+    d[2] = or_minimg(z[i], z[j], L[2]);
+    return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+}
+
+/* ------------------------------------------------------------------ */
+/* neighbour sets                                                      */
+/* ------------------------------------------------------------------ */
+
+int64_t or_neighbors_brute(int64_t n, const double L[3], double r_list,
+                           const double *x, const double *y, const double *z,
+                           int64_t *offsets, int32_t *idx, int64_t cap)
+{
+    const double rl2 = r_list * r_list;
+    double d[3];
+    int64_t total = 0;
+    offsets[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            if (dist2(L, x, y, z, i, j, d) < rl2) {
+                if (total < cap) idx[total] = (int32_t)j;
+                ++total;
+            }
+        }
+        offsets[i + 1] = total;
+    }
+    return total;
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t u = *(const int32_t *)a, v = *(const int32_t *)b;
+    return (u > v) - (u < v);
+}
+
+/* distinct values of (c + o) mod nc for o in {-1, 0, 1} */
+static int stencil_axis(int32_t c, int32_t nc, int32_t out[3])
+{
+    int m = 0;
+    for (int o = -1; o <= 1; ++o) {
+        int32_t v = ((c + o) % nc + nc) % nc;
+        int dup = 0;
+        for (int k = 0; k < m; ++k) dup |= (out[k] == v);
+        if (!dup) out[m++] = v;
+    }
+    return m;
+}
+
+int64_t or_neighbors_cells(int64_t n, const double L[3], double r_list,
+                           const double *x, const double *y, const double *z,
+                           int64_t *offsets, int32_t *idx, int64_t cap)
+{
+    int32_t nc[3];
+    for (int a = 0; a < 3; ++a) {
+        nc[a] = (int32_t)floor(L[a] / r_list);
+        if (nc[a] < 1) nc[a] = 1;
+    }
+    const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    int32_t *cx = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *cy = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *cz = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *head = malloc(sizeof(int64_t) * (size_t)ncell);
+    int64_t *next = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    or_cell_coords(n, L, nc, x, y, z, cx, cy, cz);
+    for (int64_t c = 0; c < ncell; ++c) head[c] = -1;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        int64_t c = cx[i] + (int64_t)nc[0] * (cy[i] + (int64_t)nc[1] * cz[i]);
+        next[i] = head[c];
+        head[c] = i;
+    }
+    const double rl2 = r_list * r_list;
+    double d[3];
+    int64_t total = 0;
+    offsets[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t sx[3], sy[3], sz[3];
+        int mx = stencil_axis(cx[i], nc[0], sx);
+        int my = stencil_axis(cy[i], nc[1], sy);
+        int mz = stencil_axis(cz[i], nc[2], sz);
+        int64_t row = total;
+        for (int a = 0; a < mx; ++a)
+            for (int b = 0; b < my; ++b)
+                for (int e = 0; e < mz; ++e) {
+                    int64_t c = sx[a] + (int64_t)nc[0] * (sy[b] + (int64_t)nc[1] * sz[e]);
+                    for (int64_t j = head[c]; j >= 0; j = next[j]) {
+                        if (j == i) continue;
+                        if (dist2(L, x, y, z, i, j, d) < rl2) {
+                            if (total < cap) idx[total] = (int32_t)j;
+                            ++total;
+                        }
+                    }
+                }
+        if (total <= cap) qsort(idx + row, (size_t)(total - row), sizeof(int32_t), cmp_i32);
+        offsets[i + 1] = total;
+    }
+    free(cx); free(cy); free(cz); free(head); free(next);
+    return total;
+}
+
+/* ------------------------------------------------------------------ */
+/* Lennard-Jones: pair loop with Newton's third law                    */
+/* ------------------------------------------------------------------ */
+
+static double lj_phi(const or_lj_t *p, double r2)
+{
+    double s2 = p->sigma * p->sigma / r2;
+    double s6 = s2 * s2 * s2;
+    return 4.0 * p->eps * (s6 * s6 - s6);
+}
+
+void or_forces_lj(int64_t n, const double L[3], const double *x,
+                  const double *y, const double *z, const int64_t *offsets,
+                  const int32_t *idx, const or_lj_t *p, double *fx,
+                  double *fy, double *fz, double ev[8])
+{
+    const double rc2 = p->rc * p->rc;
+    const double phi_rc = lj_phi(p, rc2);
+    double E = 0.0, Es = 0.0, W[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) fx[i] = fy[i] = fz[i] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            int64_t j = idx[k];
+            if (j <= i) continue; /* each unordered pair once */
+            double d[3];
+            double r2 = dist2(L, x, y, z, i, j, d);
+            if (!(r2 < rc2)) continue;
+            /* R = r_i - r_j is minus the displacement i -> j */
+            double R[3] = {-d[0], -d[1], -d[2]};
+            double s2 = p->sigma * p->sigma / r2;
+            double s6 = s2 * s2 * s2;
+            /* -(1/r) dPhi/dr */
+            double fs = 24.0 * p->eps * (2.0 * s6 * s6 - s6) / r2;
+            fx[i] += fs * R[0]; fy[i] += fs * R[1]; fz[i] += fs * R[2];
+            fx[j] -= fs * R[0]; fy[j] -= fs * R[1]; fz[j] -= fs * R[2];
+            double phi = 4.0 * p->eps * (s6 * s6 - s6);
+            E += phi;
+            Es += phi - phi_rc;
+            W[0] += fs * R[0] * R[0]; W[1] += fs * R[1] * R[1];
+            W[2] += fs * R[2] * R[2]; W[3] += fs * R[0] * R[1];
+            W[4] += fs * R[0] * R[2]; W[5] += fs * R[1] * R[2];
+        }
+    }
+    ev[0] = E; ev[1] = Es;
+    for (int a = 0; a < 6; ++a) ev[2 + a] = W[a];
+}
+
+/* ------------------------------------------------------------------ */
+/* Embedded-atom method, Finnis-Sinclair form, three steps             */
+/* ------------------------------------------------------------------ */
+
+static double fs_V(const or_fs_t *p, double r)
+{
+    double t = r - p->c;
+    return t * t * (p->c0 + p->c1 * r + p->c2 * r * r);
+}
+
+static double fs_dV(const or_fs_t *p, double r)
+{
+    double t = r - p->c;
+    return 2.0 * t * (p->c0 + p->c1 * r + p->c2 * r * r) +
+           t * t * (p->c1 + 2.0 * p->c2 * r);
+}
+
+void or_forces_eam(int64_t n, const double L[3], const double *x,
+                   const double *y, const double *z, const int64_t *offsets,
+                   const int32_t *idx, const or_fs_t *p, double *rho,
+                   double *fprime, double *fx, double *fy, double *fz,
+                   double *e_atom, double ev[8])
+{
+    const double d2 = p->d * p->d, c2 = p->c * p->c;
+    double d[3];
+    /* step 1: localization function rho_i = sum_{j != i} psi(r_ij) */
+    for (int64_t i = 0; i < n; ++i) rho[i] = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            int64_t j = idx[k];
+            if (j <= i) continue;
+            double r2 = dist2(L, x, y, z, i, j, d);
+            if (!(r2 < d2)) continue;
+            double t = sqrt(r2) - p->d;
+            rho[i] += t * t;
+            rho[j] += t * t;
+        }
+    /* step 2: embedding energy F_i(rho_i) and its derivative */
+    double Eemb = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double F = 0.0, Fp = 0.0;
+        if (rho[i] > 0.0) {
+            double s = sqrt(rho[i]);
+            F = -p->A * s;
+            Fp = -p->A / (2.0 * s);
+        }
+        fprime[i] = Fp;
+        Eemb += F;
+        if (e_atom) e_atom[i] = F;
+        fx[i] = fy[i] = fz[i] = 0.0;
+    }
+    /* step 3: pair interaction and forces */
+    double Epair = 0.0, W[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            int64_t j = idx[k];
+            if (j <= i) continue;
+            double r2 = dist2(L, x, y, z, i, j, d);
+            if (!(r2 < d2) && !(r2 < c2)) continue;
+            double r = sqrt(r2);
+            double dUdr = 0.0; /* dU/dr_ij with rho_i, rho_j frozen */
+            if (r2 < d2) dUdr += (fprime[i] + fprime[j]) * 2.0 * (r - p->d);
+            if (r2 < c2) {
+                double V = fs_V(p, r);
+                dUdr += fs_dV(p, r);
+                Epair += V;
+                if (e_atom) {
+                    e_atom[i] += 0.5 * V;
+                    e_atom[j] += 0.5 * V;
+                }
+            }
+            double R[3] = {-d[0], -d[1], -d[2]};
+            double g = -dUdr / r; /* F_i = g R */
+            fx[i] += g * R[0]; fy[i] += g * R[1]; fz[i] += g * R[2];
+            fx[j] -= g * R[0]; fy[j] -= g * R[1]; fz[j] -= g * R[2];
+            W[0] += g * R[0] * R[0]; W[1] += g * R[1] * R[1];
+            W[2] += g * R[2] * R[2]; W[3] += g * R[0] * R[1];
+            W[4] += g * R[0] * R[2]; W[5] += g * R[1] * R[2];
+        }
+    ev[0] = Eemb + Epair;
+    ev[1] = Eemb;
+    for (int a = 0; a < 6; ++a) ev[2 + a] = W[a];
+}
+
+/* ------------------------------------------------------------------ */
+/* velocity Verlet with the displacement rebuild rule                  */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t *off;
+    int32_t *idx;
+    int64_t cap;
+} list_t;
+
+static int build_list(int64_t n, const double L[3], double r_list,
+                      const double *x, const double *y, const double *z,
+                      list_t *l, int reverse)
+{
+    int64_t need = or_neighbors_cells(n, L, r_list, x, y, z, l->off, l->idx, l->cap);
+    if (need > l->cap) {
+        free(l->idx);
+        l->cap = need + need / 4 + 16;
+        l->idx = malloc(sizeof(int32_t) * (size_t)l->cap);
+        if (!l->idx) return -1;
+        or_neighbors_cells(n, L, r_list, x, y, z, l->off, l->idx, l->cap);
+    }
+    if (reverse) {
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t a = l->off[i], b = l->off[i + 1] - 1;
+            while (a < b) {
+                int32_t t = l->idx[a]; l->idx[a] = l->idx[b]; l->idx[b] = t;
+                ++a; --b;
+            }
+        }
+    }
+    return 0;
+}
+
+/* forces on the current list; returns the potential energy that the
+ * energy-conservation checks follow (E_shift for LJ, E_total for EAM) */
+static double eval_forces(int64_t n, const double L[3], const double *x,
+                          const double *y, const double *z, const list_t *l,
+                          const or_md_params_t *p, double *fx, double *fy,
+                          double *fz, double *rho, double *fp)
+{
+    double ev[8];
+    if (p->potential == OR_POT_LJ) {
+        or_forces_lj(n, L, x, y, z, l->off, l->idx, &p->lj, fx, fy, fz, ev);
+        return ev[1];
+    }
+    or_forces_eam(n, L, x, y, z, l->off, l->idx, &p->fs, rho, fp, fx, fy, fz, NULL, ev);
+    return ev[0];
+}
+
+static double kinetic(int64_t n, const double *vx, const double *vy,
+                      const double *vz, double mass)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
+    return 0.5 * mass * s;
+}
+
+int64_t or_md_run(int64_t n, const double L[3], double *x, double *y,
+                  double *z, double *vx, double *vy, double *vz,
+                  const or_md_params_t *p, int64_t steps, double *epot,
+                  double *ekin)
+{
+    size_t nb = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *fx = malloc(nb), *fy = malloc(nb), *fz = malloc(nb);
+    double *xr = malloc(nb), *yr = malloc(nb), *zr = malloc(nb);
+    double *rho = malloc(nb), *fp = malloc(nb);
+    list_t l;
+    l.off = malloc(sizeof(int64_t) * (size_t)(n + 1));
+    l.cap = 64 * n + 16;
+    l.idx = malloc(sizeof(int32_t) * (size_t)l.cap);
+    int64_t builds = -1;
+    if (!fx || !fy || !fz || !xr || !yr || !zr || !rho || !fp || !l.off || !l.idx) goto out;
+
+    const double half_skin2 = 0.25 * p->skin * p->skin;
+    const double hk = 0.5 * p->dt * p->force_to_accel / p->mass;
+
+    or_wrap(n, L, x, y, z);
+    if (build_list(n, L, p->r_list, x, y, z, &l, p->reverse_order)) goto out;
+    builds = 1;
+    memcpy(xr, x, nb); memcpy(yr, y, nb); memcpy(zr, z, nb);
+    double ep = eval_forces(n, L, x, y, z, &l, p, fx, fy, fz, rho, fp);
+    if (epot) epot[0] = ep;
+    if (ekin) ekin[0] = kinetic(n, vx, vy, vz, p->mass);
+
+    for (int64_t s = 1; s <= steps; ++s) {
+        double maxd2 = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] += hk * fx[i]; vy[i] += hk * fy[i]; vz[i] += hk * fz[i];
+            x[i] += p->dt * vx[i]; y[i] += p->dt * vy[i]; z[i] += p->dt * vz[i];
+            double dx = or_minimg(xr[i], x[i], L[0]);
+            double dy = or_minimg(yr[i], y[i], L[1]);
+            double dz = or_minimg(zr[i], z[i], L[2]);
+            double d2 = (dx * dx + dy * dy) + dz * dz;
+            if (d2 > maxd2) maxd2 = d2;
+        }
+        if (maxd2 > half_skin2) {
+            or_wrap(n, L, x, y, z);
+            if (build_list(n, L, p->r_list, x, y, z, &l, p->reverse_order)) { builds = -1; goto out; }
+            ++builds;
+            memcpy(xr, x, nb); memcpy(yr, y, nb); memcpy(zr, z, nb);
+        }
+        ep = eval_forces(n, L, x, y, z, &l, p, fx, fy, fz, rho, fp);
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] += hk * fx[i]; vy[i] += hk * fy[i]; vz[i] += hk * fz[i];
+        }
+        if (epot) epot[s] = ep;
+        if (ekin) ekin[s] = kinetic(n, vx, vy, vz, p->mass);
+    }
+out:
+    free(fx); free(fy); free(fz); free(xr); free(yr); free(zr);
+    free(rho); free(fp); free(l.off); free(l.idx);
+    return builds;
+}

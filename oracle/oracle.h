@@ -1,0 +1,138 @@
+/*
+ * FP64 CPU oracle for the short-range molecular-dynamics hot path of
+ * Mangiardi & Meyer, "A hybrid algorithm for parallel molecular dynamics
+ * simulations" (arXiv:1611.00075).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously
+ * correct statement of what the GPU path computes.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark load it.  It
+ * shares no code, header, table or helper with the HIP library, and the HIP
+ * library never calls it.
+ *
+ * Conventions (all functions):
+ *   - positions, velocities, forces are FP64 structure-of-arrays in the
+ *     caller's atom order;
+ *   - the box is orthorhombic and periodic on every axis, edge lengths L[3];
+ *   - every cutoff test is strict (r^2 < rc^2);
+ *   - no function allocates memory that outlives the call; outputs are
+ *     caller-owned.
+ *
+ * Parity pins: every function here is checked by the CPU tests against
+ * brute force, closed-form lattice sums, finite differences of the energy,
+ * conservation laws or published constants.  No function is "parity
+ * unpinned".
+ */
+#ifndef MD_ORACLE_H
+#define MD_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- periodic geometry (Sec. 3.3: periodic boundaries on every axis) ---- */
+
+/* Wrap each coordinate into [0, L): w = x - L*floor(x/L), then one
+ * correction step each way.  FP64, correctly rounded division, no FMA. */
+void or_wrap(int64_t n, const double L[3], double *x, double *y, double *z);
+
+/* Cell coordinates of wrapped positions on an nc[0] x nc[1] x nc[2] grid:
+ * c = (int)(w * (nc/L)), clamped to nc-1.  (Sec. 2.1: the volume is divided
+ * into small cells.) */
+void or_cell_coords(int64_t n, const double L[3], const int32_t nc[3],
+                    const double *x, const double *y, const double *z,
+                    int32_t *cx, int32_t *cy, int32_t *cz);
+
+/* Minimum-image displacement component: dx = b - a, shifted by one box
+ * length when it exceeds half a box. */
+double or_minimg(double a, double b, double L);
+
+/* ---- Verlet neighbour sets (Sec. 3.3: list cutoff larger than the
+ * potential cutoff) ---- */
+
+/* Full neighbour set N(i) = { j != i : r_ij^2 < r_list^2 } by the O(N^2)
+ * definition.  Row i lists j in ascending order.  offsets has n+1 entries.
+ * Returns the total number of entries; idx is written only if the total fits
+ * in cap. */
+int64_t or_neighbors_brute(int64_t n, const double L[3], double r_list,
+                           const double *x, const double *y, const double *z,
+                           int64_t *offsets, int32_t *idx, int64_t cap);
+
+/* The same set through a cell list (cells of edge >= r_list, 27 neighbour
+ * cells with duplicates removed when a box holds fewer than three cells).
+ * Rows are sorted ascending so that the result is comparable entry by entry
+ * with or_neighbors_brute.  Positions must already be wrapped. */
+int64_t or_neighbors_cells(int64_t n, const double L[3], double r_list,
+                           const double *x, const double *y, const double *z,
+                           int64_t *offsets, int32_t *idx, int64_t cap);
+
+/* ---- potentials ---- */
+
+typedef struct {
+    double eps, sigma, rc;
+} or_lj_t;
+
+/* Finnis-Sinclair form used for the metal benchmark:
+ *   psi(r) = (r-d)^2 for r<d, F(rho) = -A sqrt(rho),
+ *   V(r)   = (r-c)^2 (c0 + c1 r + c2 r^2) for r<c. */
+typedef struct {
+    double A, d, c, c0, c1, c2;
+} or_fs_t;
+
+/* Lennard-Jones forces by the pair loop with Newton's third law (Sec. 2.2,
+ * pair-force listing): each unordered pair {i,j} with r < rc is visited once
+ * from the lower index, F = -(1/r) dPhi/dr R with R = r_i - r_j is added to
+ * f_i and subtracted from f_j.  The list may be any superset of the pairs
+ * within rc (a full list; only entries j > i are used).
+ * ev[8] receives: E (truncated), E_shift (each pair shifted by -Phi(rc)),
+ * virial W_xx, W_yy, W_zz, W_xy, W_xz, W_yz (sum over pairs of f_s R_a R_b). */
+void or_forces_lj(int64_t n, const double L[3], const double *x,
+                  const double *y, const double *z, const int64_t *offsets,
+                  const int32_t *idx, const or_lj_t *p, double *fx,
+                  double *fy, double *fz, double ev[8]);
+
+/* Embedded-atom forces in the three steps of Sec. 3.1 (after Eqs. 1-2):
+ * (1) rho_i = sum_j psi(r_ij) by the pair loop, (2) F_i(rho_i) per atom,
+ * (3) the pair interaction and the forces by the pair loop.
+ * Outputs rho[n], fprime[n] (= F'(rho_i)), forces, e_atom[n] (per-atom
+ * energy F(rho_i) + 1/2 sum_j V(r_ij); may be NULL) and ev[8]:
+ * E_total, E_embed, then the six virial components. */
+void or_forces_eam(int64_t n, const double L[3], const double *x,
+                   const double *y, const double *z, const int64_t *offsets,
+                   const int32_t *idx, const or_fs_t *p, double *rho,
+                   double *fprime, double *fx, double *fy, double *fz,
+                   double *e_atom, double ev[8]);
+
+/* ---- velocity-Verlet molecular dynamics (Sec. 3.3) ---- */
+
+enum { OR_POT_LJ = 0, OR_POT_EAM = 1 };
+
+typedef struct {
+    int32_t potential;      /* OR_POT_LJ or OR_POT_EAM */
+    or_lj_t lj;
+    or_fs_t fs;
+    double r_list;          /* potential cutoff + skin */
+    double skin;
+    double dt;
+    double mass;
+    double force_to_accel;  /* 1 in reduced units; 1/103.6427 for eV, A, amu, fs */
+    int32_t reverse_order;  /* 1: visit each neighbour row in reverse order */
+} or_md_params_t;
+
+/* Runs `steps` velocity-Verlet steps in place.  Before the first step the
+ * positions are wrapped, the list is built and the forces are evaluated.
+ * Each step: half kick, drift, rebuild (wrap + new list) iff some atom has
+ * moved more than skin/2 since the last build, forces, half kick.
+ * Per step k (0 = the initial state, k = 1..steps after step k) the arrays
+ * epot[k], ekin[k] (may be NULL) receive the potential energy (E_shift for
+ * LJ, E_total for EAM) and the kinetic energy.  Returns the number of list
+ * builds including the first, or a negative value on allocation failure. */
+int64_t or_md_run(int64_t n, const double L[3], double *x, double *y,
+                  double *z, double *vx, double *vy, double *vz,
+                  const or_md_params_t *p, int64_t steps, double *epot,
+                  double *ekin);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

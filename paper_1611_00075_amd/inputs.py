@@ -1,0 +1,228 @@
+"""Seeded synthetic inputs for the molecular-dynamics hot path.
+
+This module only *draws* inputs: lattice sites, voids, clusters and
+Maxwell-Boltzmann velocities.  It holds none of the method's arithmetic
+(no binning, neighbour search, forces or integration), so both the FP64
+oracle and the GPU library may be fed from it.
+
+Every generator is deterministic in its seed.  Random numbers come from
+numpy's PCG64 generator, one independent stream per (seed, purpose) pair.
+
+The workloads stand in for the paper's benchmark geometries (Sec. 3.1:
+the bulk fcc crystal Cu105, the porous sintered copper, the phononic crystal
+with vacuum), which are not available: homogeneous fcc, fcc riddled with
+spherical voids, and a slab with a vacuum gap holding a denser cluster.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# eV per (amu * Angstrom^2 / fs^2): converts m v^2 into eV in metal units
+AMU_A2_FS2_IN_EV = 103.6427
+# Boltzmann constant in eV/K
+KB_EV = 8.617333262e-5
+# copper
+CU_MASS_AMU = 63.546
+CU_A0 = 3.615
+
+# Cu-like Finnis-Sinclair parameters for psi(r) = (r-d)^2, F = -A sqrt(rho),
+# V(r) = (r-c)^2 (c0 + c1 r + c2 r^2).  They are the solution of four
+# conditions on the perfect fcc lattice at a = 3.615 A (cohesive energy
+# 3.54 eV, zero pressure, bulk modulus 138 GPa, unrelaxed vacancy formation
+# energy 1.28 eV); the CPU tests re-derive each condition.
+FS_CU = dict(A=0.6904081156, d=4.4, c=3.25,
+             c0=12.35488532, c1=-9.40961636, c2=1.84672514)
+
+FCC_BASIS = np.array([[0.0, 0.0, 0.0],
+                      [0.5, 0.5, 0.0],
+                      [0.5, 0.0, 0.5],
+                      [0.0, 0.5, 0.5]])
+
+
+@dataclasses.dataclass
+class System:
+    """A periodic orthorhombic system: FP64 positions and velocities (n, 3)."""
+    name: str
+    L: np.ndarray            # (3,) box edge lengths
+    x: np.ndarray            # (n, 3) float64
+    v: np.ndarray            # (n, 3) float64
+    mass: float
+    kB: float                # Boltzmann constant in the system's energy unit
+    e_unit: float            # m v^2 -> energy factor (1 reduced, 103.6427 metal)
+    meta: dict
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+def rng_for(seed: int, purpose: str) -> np.random.Generator:
+    """Independent PCG64 stream for a (seed, purpose) pair."""
+    key = [int(seed)] + [ord(c) for c in purpose]
+    return np.random.default_rng(np.random.SeedSequence(key))
+
+
+def fcc_sites(nx: int, ny: int, nz: int, a: float) -> np.ndarray:
+    """fcc sites in id order: id = 4*((ix*ny + iy)*nz + iz) + b."""
+    ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz),
+                             indexing="ij")
+    cells = np.stack([ix, iy, iz], axis=-1).reshape(-1, 1, 3).astype(np.float64)
+    return ((cells + FCC_BASIS[None]) * a).reshape(-1, 3)
+
+
+def fcc_lattice_constant(density: float) -> float:
+    return (4.0 / density) ** (1.0 / 3.0)
+
+
+def maxwell_boltzmann(n: int, T: float, mass: float, kB: float, e_unit: float,
+                      rng: np.random.Generator) -> np.ndarray:
+    """Gaussian velocities with zero total momentum, rescaled so that
+    2 KE / ((3n-3) kB) equals T exactly (KE = 1/2 m v^2 * e_unit)."""
+    v = rng.standard_normal((n, 3))
+    v -= v.mean(axis=0, keepdims=True)
+    if n < 2 or T <= 0.0:
+        return np.zeros((n, 3))
+    ke = 0.5 * mass * e_unit * float(np.sum(v * v))
+    target = 0.5 * (3 * n - 3) * kB * T
+    v *= math.sqrt(target / ke)
+    return v
+
+
+def temperature(v: np.ndarray, mass: float, kB: float, e_unit: float) -> float:
+    n = v.shape[0]
+    ke = 0.5 * mass * e_unit * float(np.sum(v * v))
+    return 2.0 * ke / ((3 * n - 3) * kB)
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+
+def lj_fcc(ncell: int = 10, density: float = 0.8442, T: float = 0.72,
+           seed: int = 1001) -> System:
+    """Lennard-Jones fcc crystal in reduced units (10^3 cells = 4,000 atoms)."""
+    a = fcc_lattice_constant(density)
+    x = fcc_sites(ncell, ncell, ncell, a)
+    L = np.full(3, ncell * a)
+    v = maxwell_boltzmann(len(x), T, 1.0, 1.0, 1.0, rng_for(seed, "velocity"))
+    return System("lj_fcc", L, x, v, 1.0, 1.0, 1.0,
+                  dict(a=a, density=density, T=T, seed=seed, ncell=ncell))
+
+
+def lj_voids(ncell: int = 80, density: float = 0.8442, T: float = 0.72,
+             remove_frac: float = 0.40, rmin: float = 3.0, rmax: float = 8.0,
+             seed: int = 1002) -> System:
+    """fcc Lennard-Jones crystal riddled with random spherical voids.
+
+    Void centres are uniform in the box, radii uniform in [rmin, rmax];
+    a site is removed when its periodic distance to a centre is strictly
+    below the radius.  Voids are added until at least `remove_frac` of the
+    sites are gone (80^3 cells: 2,048,000 sites, about 1.23 M atoms left)."""
+    a = fcc_lattice_constant(density)
+    n = ncell
+    L = n * a
+    keep = np.ones((n, n, n, 4), dtype=bool)
+    rng = rng_for(seed, "voids")
+    target = int(math.ceil(remove_frac * keep.size))
+    removed = 0
+    nvoid = 0
+    while removed < target:
+        c = rng.uniform(0.0, L, size=3)
+        R = rng.uniform(rmin, rmax)
+        lo = np.floor((c - R) / a).astype(int) - 1
+        hi = np.floor((c + R) / a).astype(int) + 1
+        rng_ax = [np.arange(lo[k], hi[k] + 1) for k in range(3)]
+        I, J, K = np.meshgrid(*rng_ax, indexing="ij")
+        cells = np.stack([I, J, K], -1).reshape(-1, 1, 3)
+        pos = (cells + FCC_BASIS[None]) * a          # unwrapped image positions
+        d = pos - c
+        r2 = np.sum(d * d, axis=-1)
+        hit = r2 < R * R
+        ci = np.mod(cells.reshape(-1, 3), n)
+        hi_idx = np.nonzero(hit)
+        cc = ci[hi_idx[0]]
+        bb = hi_idx[1]
+        before = keep[cc[:, 0], cc[:, 1], cc[:, 2], bb]
+        removed += int(np.count_nonzero(before))
+        keep[cc[:, 0], cc[:, 1], cc[:, 2], bb] = False
+        nvoid += 1
+    x = fcc_sites(n, n, n, a)[keep.reshape(-1)]
+    v = maxwell_boltzmann(len(x), T, 1.0, 1.0, 1.0, rng_for(seed, "velocity"))
+    return System("lj_voids", np.full(3, L), x, v, 1.0, 1.0, 1.0,
+                  dict(a=a, density=density, T=T, seed=seed, ncell=n,
+                       sites=keep.size, voids=nvoid))
+
+
+def lj_slab_cluster(nxy: int = 251, nz_slab: int = 125, density: float = 0.8442,
+                    cluster_density: float = 1.05, cluster_atoms: int = 2_000_000,
+                    T: float = 0.72, seed: int = 1004) -> System:
+    """fcc slab filling the lower half of a cubic periodic box (vacuum above)
+    with a denser spherical fcc cluster at the slab centre.
+
+    The box edge is nxy fcc cells of the slab lattice in every direction;
+    slab sites within R + 0.5 of the centre are removed and the sphere of
+    radius R is re-filled with fcc at `cluster_density`, R chosen so that the
+    sphere holds about `cluster_atoms` atoms (defaults: about 32 M atoms)."""
+    a = fcc_lattice_constant(density)
+    L = nxy * a
+    slab = fcc_sites(nxy, nxy, nz_slab, a)
+    centre = np.array([0.5 * L, 0.5 * L, 0.5 * nz_slab * a])
+    R = (3.0 * cluster_atoms / (4.0 * math.pi * cluster_density)) ** (1.0 / 3.0)
+    d = slab - centre
+    keep = np.sum(d * d, axis=1) >= (R + 0.5) ** 2
+    slab = slab[keep]
+    del d, keep
+    a2 = fcc_lattice_constant(cluster_density)
+    m = int(math.ceil(R / a2)) + 1
+    cl = fcc_sites(2 * m, 2 * m, 2 * m, a2) - m * a2 + centre
+    dc = cl - centre
+    cl = cl[np.sum(dc * dc, axis=1) < R * R]
+    x = np.concatenate([slab, cl])
+    v = maxwell_boltzmann(len(x), T, 1.0, 1.0, 1.0, rng_for(seed, "velocity"))
+    return System("lj_slab_cluster", np.full(3, L), x, v, 1.0, 1.0, 1.0,
+                  dict(a=a, density=density, cluster_density=cluster_density,
+                       R=R, T=T, seed=seed, slab_atoms=len(slab),
+                       cluster_atoms=len(cl)))
+
+
+def eam_cu(ncell: int = 100, a: float = CU_A0, T: float = 600.0,
+           seed: int = 1003) -> System:
+    """fcc Cu-like metal in eV, Angstrom, amu, fs (100^3 cells = 4 M atoms)."""
+    x = fcc_sites(ncell, ncell, ncell, a)
+    v = maxwell_boltzmann(len(x), T, CU_MASS_AMU, KB_EV, AMU_A2_FS2_IN_EV,
+                          rng_for(seed, "velocity"))
+    return System("eam_cu", np.full(3, ncell * a), x, v, CU_MASS_AMU, KB_EV,
+                  AMU_A2_FS2_IN_EV, dict(a=a, T=T, seed=seed, ncell=ncell))
+
+
+def jitter(sys: System, sigma: float, seed: int) -> System:
+    """Copy of `sys` with Gaussian position noise of width sigma (a stand-in
+    for a thermalised snapshot in per-call parity tests)."""
+    rng = rng_for(seed, "jitter")
+    x = sys.x + rng.normal(0.0, sigma, size=sys.x.shape)
+    return dataclasses.replace(sys, x=x, meta=dict(sys.meta, jitter=sigma))
+
+
+def random_gas(n: int, L, seed: int, min_dist: float = 0.0) -> np.ndarray:
+    """n uniform random points in a box (optionally rejecting points closer
+    than min_dist to an earlier point, by periodic distance)."""
+    rng = rng_for(seed, "gas")
+    L = np.asarray(L, dtype=np.float64)
+    if min_dist <= 0.0:
+        return rng.uniform(0.0, 1.0, size=(n, 3)) * L
+    pts = []
+    while len(pts) < n:
+        p = rng.uniform(0.0, 1.0, size=3) * L
+        ok = True
+        for q in pts:
+            d = p - q
+            d -= L * np.round(d / L)
+            if float(np.dot(d, d)) < min_dist * min_dist:
+                ok = False
+                break
+        if ok:
+            pts.append(p)
+    return np.array(pts)

@@ -1,0 +1,156 @@
+"""Pins for the oracle's Lennard-Jones forces, energies and virial.
+
+Energies are pinned to fcc lattice sums built from textbook shell counts and
+to the published infinite-range sums A12, A6; forces and virial to central
+finite differences of the energy; momentum to Newton's third law."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1611_00075_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _lj(r2):
+    s6 = 1.0 / r2 ** 3
+    return 4.0 * (s6 * s6 - s6)
+
+
+def _lattice_shells(kmax):
+    """Squared distances (units a_nn^2) and multiplicities of fcc shells,
+    from the textbook shell counts."""
+    g = json.load(open(os.path.join(GOLD, "fcc_lattice.json")))
+    return [(k + 1, g["fcc_shell_counts"][k]) for k in range(kmax)]
+
+
+def test_lj_fcc_lattice_energy_closed_form(orc):
+    s = inputs.lj_fcc(ncell=6)
+    x = orc.wrap(s.x, s.L)
+    off, idx = orc.neighbors_cells(x, s.L, 2.8)
+    f, ev = orc.forces_lj(x, s.L, off, idx, rc=2.5)
+    ann2 = (s.meta["a"] ** 2) / 2.0
+    # shells with k a_nn^2 < rc^2 = 6.25: k = 1..4 (k = 5 is at 2.656 sigma)
+    shells = [(k, m) for (k, m) in _lattice_shells(5) if k * ann2 < 6.25]
+    assert [k for k, _ in shells] == [1, 2, 3, 4]
+    e_atom = 0.5 * sum(m * _lj(k * ann2) for k, m in shells)
+    shift = 0.5 * sum(m for _, m in shells) * _lj(6.25)
+    n = len(x)
+    assert ev[0] / n == pytest.approx(e_atom, rel=1e-12)
+    assert ev[1] / n == pytest.approx(e_atom - shift, rel=1e-12)
+    assert e_atom == pytest.approx(-6.773368, abs=2e-6)
+    # virial trace: sum over pairs of f_s r^2 = -sum r dPhi/dr
+    w_atom = 0.5 * sum(m * (48.0 / (k * ann2) ** 6 - 24.0 / (k * ann2) ** 3)
+                       for k, m in shells)
+    assert (ev[2] + ev[3] + ev[4]) / n == pytest.approx(w_atom, rel=1e-11)
+    # cubic symmetry: isotropic diagonal, zero off-diagonal, zero forces
+    assert ev[2] == pytest.approx(ev[3], rel=1e-12) == pytest.approx(ev[4], rel=1e-12)
+    assert np.abs(ev[5:]).max() < 1e-9 * abs(ev[2])
+    assert np.abs(f).max() < 1e-11
+
+
+def test_lj_infinite_range_matches_published_lattice_sums(orc):
+    """E/N -> 2 eps (A12 (sigma/a_nn)^12 - A6 (sigma/a_nn)^6) as rc grows;
+    the missing tail beyond rc is bounded by the continuum r^-6 tail."""
+    g = json.load(open(os.path.join(GOLD, "fcc_lattice.json")))
+    density = 0.8442
+    s = inputs.lj_fcc(ncell=12, density=density)
+    x = orc.wrap(s.x, s.L)
+    rc = 9.0
+    off, idx = orc.neighbors_cells(x, s.L, rc)
+    _, ev = orc.forces_lj(x, s.L, off, idx, rc=rc)
+    ann = s.meta["a"] / math.sqrt(2.0)
+    e_inf = 2.0 * (g["fcc_A12"] * ann ** -12 - g["fcc_A6"] * ann ** -6)
+    tail = -8.0 * math.pi * density / (3.0 * rc ** 3)   # 1/2 rho int 4 pi r^2 (-4 r^-6)
+    assert ev[0] / len(x) == pytest.approx(e_inf - tail, abs=2e-3)
+
+
+def _energy(orc, x, L, rc=2.5, r_list=2.9):
+    off, idx = orc.neighbors_brute(x, L, r_list)
+    return orc.forces_lj(x, L, off, idx, rc=rc)
+
+
+def test_lj_forces_are_minus_energy_gradient(orc):
+    s = inputs.jitter(inputs.lj_fcc(ncell=3), 0.05, seed=11)
+    L = s.L
+    x = orc.wrap(s.x, L)
+    f, ev = _energy(orc, x, L)
+    h = 1e-6
+    rng = np.random.default_rng(5)
+    for i in rng.choice(len(x), 8, replace=False):
+        for a in range(3):
+            xp = x.copy(); xp[i, a] += h
+            xm = x.copy(); xm[i, a] -= h
+            ep = _energy(orc, xp, L)[1][0]
+            em = _energy(orc, xm, L)[1][0]
+            fd = -(ep - em) / (2 * h)
+            assert f[i, a] == pytest.approx(fd, rel=1e-6, abs=1e-6)
+
+
+def test_lj_virial_is_minus_strain_derivative(orc):
+    """W_aa = -dE/ds_a under x_a -> s_a x_a, L_a -> s_a L_a (no pair crosses rc)."""
+    s = inputs.jitter(inputs.lj_fcc(ncell=3), 0.03, seed=12)
+    x = orc.wrap(s.x, s.L)
+    f, ev = _energy(orc, x, s.L)
+    h = 1e-6
+    for a in range(3):
+        sc = np.ones(3); sc[a] = 1 + h
+        ep = _energy(orc, x * sc, s.L * sc)[1][0]
+        sc[a] = 1 - h
+        em = _energy(orc, x * sc, s.L * sc)[1][0]
+        assert ev[2 + a] == pytest.approx(-(ep - em) / (2 * h), rel=1e-6)
+    # W_xy = -dE/dg under the shear x -> x + g y applied to all displacements;
+    # for an orthorhombic box the sheared pair vectors are R + g R_y e_x
+    off, idx = orc.neighbors_brute(x, s.L, 2.9)
+    e_of = lambda g: _sheared_energy(x, s.L, off, idx, g)
+    assert ev[5] == pytest.approx(-(e_of(h) - e_of(-h)) / (2 * h), rel=1e-5, abs=1e-8)
+
+
+def _sheared_energy(x, L, off, idx, g):
+    e = 0.0
+    for i in range(len(x)):
+        for j in idx[off[i]:off[i + 1]]:
+            if j <= i:
+                continue
+            R = x[i] - x[j]
+            R -= L * np.round(R / L)
+            R = R + np.array([g * R[1], 0.0, 0.0])
+            r2 = R @ R
+            if r2 < 6.25:
+                e += _lj(r2)
+    return e
+
+
+def test_lj_newton_third_law_and_zero_net_force(orc):
+    L = np.array([8.0, 8.0, 8.0])
+    x = orc.wrap(inputs.random_gas(300, L, seed=4, min_dist=0.85), L)
+    off, idx = orc.neighbors_brute(x, L, 2.8)
+    f, ev = orc.forces_lj(x, L, off, idx)
+    scale = np.abs(f).max()
+    assert np.abs(f.sum(axis=0)).max() < 1e-12 * scale * len(x)
+    # two isolated atoms: equal and opposite, along the separation
+    L2 = np.array([20.0, 20.0, 20.0])
+    x2 = np.array([[1.0, 1.0, 1.0], [2.1, 1.3, 0.8]])
+    o2, i2 = orc.neighbors_brute(x2, L2, 2.8)
+    f2, ev2 = orc.forces_lj(x2, L2, o2, i2)
+    R = x2[0] - x2[1]
+    r2 = R @ R
+    fs = 24 * (2 / r2 ** 6 - 1 / r2 ** 3) / r2
+    assert np.allclose(f2[0], fs * R, rtol=1e-14, atol=0)
+    assert np.allclose(f2[1], -fs * R, rtol=1e-14, atol=0)
+
+
+def test_lj_cutoff_is_strict_and_list_superset_ok(orc):
+    L = np.array([20.0, 20.0, 20.0])
+    x = np.array([[1.0, 1.0, 1.0], [3.5, 1.0, 1.0], [1.0, 3.4, 1.0]])  # r = 2.5 exactly, 2.4
+    off, idx = orc.neighbors_brute(x, L, 2.8)
+    f, ev = orc.forces_lj(x, L, off, idx, rc=2.5)
+    assert f[1].tolist() == [0.0, 0.0, 0.0]
+    assert f[2, 1] != 0.0
+    # a longer list gives the same forces
+    off2, idx2 = orc.neighbors_brute(x, L, 5.0)
+    f2, ev2 = orc.forces_lj(x, L, off2, idx2, rc=2.5)
+    assert np.array_equal(f, f2) and np.array_equal(ev, ev2)
