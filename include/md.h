@@ -1,0 +1,219 @@
+/*
+ * md.h -- C ABI of the MI355X (gfx950) short-range molecular-dynamics hot
+ * path after Mangiardi & Meyer, "A hybrid algorithm for parallel molecular
+ * dynamics simulations" (arXiv:1611.00075).
+ *
+ * The path: cell binning with a counting sort into Morton-ordered cells,
+ * Verlet neighbour lists over the neighbouring cells within cutoff + skin,
+ * Lennard-Jones and embedded-atom (Finnis-Sinclair) forces, velocity-Verlet
+ * update with the displacement rebuild rule.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named x, v, xref, f are device pointers to structure-of-arrays
+ *     blocks of 3*n elements: component a of atom i is at [a*n + i].
+ *   - The caller owns every buffer, including the workspace `ws`; the library
+ *     never allocates or frees device memory.  `ws` must be at least
+ *     md_workspace_bytes() long and initialised once with md_workspace_init()
+ *     for the grid it is used with.
+ *   - Every device call enqueues its kernels on `stream` (a hipStream_t
+ *     passed as void*; NULL is the default stream) and returns without
+ *     waiting, except where a call says it synchronises.
+ *   - Return value: MD_OK (0) or a negative md_status code.  No exception or
+ *     abort crosses the ABI.  Argument errors are detected on the host before
+ *     anything is enqueued; kernel-detected conditions (non-finite
+ *     positions) are reported through the status words of md_integrate.
+ *   - Calls that share one workspace must not run concurrently.
+ *   - Atom counts are limited to n < 2^31 - 1; neighbour-list offsets are
+ *     64-bit.
+ */
+#ifndef MD_H
+#define MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+typedef enum md_status {
+    MD_OK = 0,
+    MD_ERR_ARG = -1,        /* null pointer, bad size or flag */
+    MD_ERR_BOX = -2,        /* r_list >= L/2 on some axis, or L <= 0 */
+    MD_ERR_CAPACITY = -3,   /* neighbour list larger than its buffer */
+    MD_ERR_NONFINITE = -4,  /* a kernel saw a non-finite position */
+    MD_ERR_HIP = -5,        /* a HIP runtime call failed */
+    MD_ERR_WORKSPACE = -6   /* workspace too small or not initialised */
+} md_status;
+
+/* Message for a status code (static storage, never NULL). */
+const char *md_error_string(int status);
+
+/* ---- flags ---- */
+#define MD_ENERGY        0x1  /* forces: also write energy and virial to ev */
+#define MD_PAIR_FP64     0x2  /* forces: FP64 pair arithmetic, FP64 forces */
+#define MD_NO_COMPENSATE 0x4  /* forces: plain FP32 accumulation (timing aid) */
+
+/* ---- geometry ---- */
+
+/* Orthorhombic box, periodic on every axis (Sec. 3.3).  Open boundaries are
+ * not supported. */
+typedef struct md_box {
+    double L[3];
+} md_box_t;
+
+/* Cell grid used for binning and neighbour search (Sec. 2.1: the volume is
+ * divided into small cells).  Cells have edge >= r_list / reach, so every
+ * pair closer than r_list lies within `reach` cells along each axis. */
+typedef struct md_grid {
+    double L[3];
+    double r_list;
+    double inv_cell[3];   /* nc[a] / L[a], computed on the host */
+    int32_t nc[3];        /* cells per axis: floor(reach * L / r_list) */
+    int32_t reach;        /* stencil half-width in cells (1 or 2) */
+    int64_t n_cells;
+} md_grid_t;
+
+/* Host only.  Fills *grid for a box and list cutoff r_list.  reach = 1 gives
+ * cells of edge >= r_list and the 27-cell stencil; reach = 2 gives cells of
+ * edge >= r_list/2 and the 125-cell stencil.  Stencil offsets that coincide
+ * modulo nc are visited once.  Returns MD_ERR_BOX unless
+ * 0 < r_list < L[a]/2 on every axis. */
+int md_grid_init(const md_box_t *box, double r_list, int32_t reach,
+                 md_grid_t *grid);
+
+/* Host only.  Dense Morton rank of every cell: rank[cx + nc0*(cy + nc1*cz)]
+ * is the position of the cell when all cells are sorted by the Morton
+ * (bit-interleaved) code of (cx, cy, cz).  `rank` holds n_cells entries. */
+int md_grid_cell_ranks(const md_grid_t *grid, int32_t *rank);
+
+/* ---- workspace ---- */
+
+/* Host only.  Bytes of workspace needed for up to n atoms on `grid`. */
+size_t md_workspace_bytes(const md_grid_t *grid, int64_t n);
+
+/* Uploads the Morton tables of `grid` into ws and clears the status words.
+ * Synchronises `stream` once (a host-to-device copy). */
+int md_workspace_init(const md_grid_t *grid, int64_t n, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* ---- step a1/a2: binning ---- */
+
+/* Wraps x in place into [0, L) (w = x - L floor(x/L), one correction each
+ * way, FP64), assigns each atom its cell c = (int)(w * inv_cell) clamped to
+ * nc-1, and sorts the atoms by the Morton rank of their cell with a stable
+ * counting sort.
+ * Outputs (device, caller-owned):
+ *   cell[n]                Morton rank of each atom's cell, in input order;
+ *   perm[n]                perm[k] = input index of the k-th sorted atom;
+ *                          atoms of one cell keep their input order;
+ *   cell_start[n_cells+1]  sorted atoms of the cell of rank r are
+ *                          [cell_start[r], cell_start[r+1]).
+ * Reorder per-atom arrays with md_permute afterwards. */
+int md_bin_cells(const md_grid_t *grid, int64_t n, double *x, int32_t *cell,
+                 int32_t *perm, int32_t *cell_start, void *ws, size_t ws_bytes,
+                 void *stream);
+
+/* dst[c*n + k] = src[c*n + perm[k]] for c < ncomp, k < n; elements of
+ * elem_bytes = 4, 8 or 16 bytes.  src and dst must not overlap. */
+int md_permute(int64_t n, int32_t ncomp, const int32_t *perm, const void *src,
+               void *dst, int32_t elem_bytes, void *stream);
+
+/* Scaled coordinates for the FP32 force kernels (the fractional position of
+ * Sec. 4.1, "fetch" and "dist"): xs[4i+a] = round(x[a*n+i] * 2^32 / L[a])
+ * modulo 2^32, so that the 32-bit difference of two atoms is their periodic
+ * minimum-image displacement in units of L[a]/2^32.  xs[4i+3] is set to 0;
+ * md_forces_eam stores F'(rho_i) there between its passes. */
+int md_scale_positions(const md_box_t *box, int64_t n, const double *x,
+                       uint32_t *xs, void *stream);
+
+/* ---- step a3: neighbour lists ---- */
+
+/* Full Verlet lists (Sec. 3.3): row i holds every j != i with
+ * r_ij^2 < r_list^2, r_ij^2 = (dx*dx + dy*dy) + dz*dz of the minimum-image
+ * displacement dx = x_j - x_i (shifted by L when |dx| > L/2), in FP64 with
+ * no contraction.  j in N(i) iff i in N(j).  Positions must be the wrapped,
+ * sorted output of md_bin_cells + md_permute, cell_start its output.
+ * Outputs: offsets[n+1] (int64, row i is idx[offsets[i] .. offsets[i+1])),
+ * idx[capacity] (sorted atom indices; order within a row is unspecified but
+ * deterministic).  Synchronises `stream` once to read the total, stores it
+ * in *needed (host) and returns MD_ERR_CAPACITY, without writing idx, when
+ * it exceeds `capacity`. */
+int md_build_neighbors(const md_grid_t *grid, int64_t n, const double *x,
+                       const int32_t *cell_start, int64_t *offsets,
+                       int32_t *idx, int64_t capacity, int64_t *needed,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* ---- step a4: Lennard-Jones ---- */
+
+typedef struct md_lj {
+    double eps, sigma, rc;
+} md_lj_t;
+
+/* Lennard-Jones forces from a full list (the pair loop of Sec. 2.2, with
+ * every pair visited from both sides so that no force is scattered):
+ *   F_i = sum_{j in N(i), r < rc} 24 eps s6 (2 s6 - 1) / r^2 (r_i - r_j),
+ *   s6 = (sigma/r)^6, truncated at rc.
+ * Default: displacements from the scaled coordinates xs, pair arithmetic in
+ * FP32, per-atom sums compensated (Kahan) in FP32 and combined across lanes
+ * in FP64; f is float[3n].  With MD_PAIR_FP64: displacements from x in
+ * FP64 (minimum image as in md_build_neighbors), all arithmetic FP64, f is
+ * double[3n]; xs may be NULL.  f is overwritten.
+ * With MD_ENERGY, ev[8] (device) receives E = 1/2 sum 4 eps (s12 - s6),
+ * E_shift (each pair shifted by -Phi(rc)) and the virial
+ * W_ab = 1/2 sum_i sum_j f_s R_a R_b in the order xx, yy, zz, xy, xz, yz,
+ * reduced in FP64 in a fixed order. */
+int md_forces_lj(const md_box_t *box, int64_t n, const double *x,
+                 const uint32_t *xs, const int64_t *offsets,
+                 const int32_t *idx, const md_lj_t *lj, void *f, double *ev,
+                 int32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- steps a5/a6: embedded-atom method ---- */
+
+/* Finnis-Sinclair form of Eqs. (1)-(2): psi(r) = (r-d)^2 for r < d,
+ * F(rho) = -A sqrt(rho) (F = F' = 0 at rho = 0), V(r) = (r-c)^2
+ * (c0 + c1 r + c2 r^2) for r < c. */
+typedef struct md_fs {
+    double A, d, c, c0, c1, c2;
+} md_fs_t;
+
+/* The three steps of Sec. 3.1: (1) rho_i = sum_j psi(r_ij) over the full
+ * list; (2) F_i, F'_i per atom (fused into the first kernel's epilogue);
+ * (3) F_i = -sum_j [(F'_i + F'_j) psi'(r) + V'(r)] (r_i - r_j)/r.
+ * FP32 pair arithmetic from the scaled coordinates xs (written by
+ * md_scale_positions; xs[4i+3] is overwritten with F'_i), compensated FP32
+ * sums.  Outputs: rho[n], fprime[n] (float), f float[3n] (overwritten); with
+ * MD_ENERGY, ev[8] = E_total, E_embed, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz. */
+int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs,
+                  const int64_t *offsets, const int32_t *idx,
+                  const md_fs_t *fs, float *rho, float *fprime, float *f,
+                  double *ev, int32_t flags, void *ws, size_t ws_bytes,
+                  void *stream);
+
+/* ---- step a7: velocity Verlet ---- */
+
+#define MD_KICK_DRIFT 1   /* v += dt/2 a f; x += dt v; rebuild check */
+#define MD_KICK       2   /* v += dt/2 a f; optional kinetic energy */
+
+/* One half of a velocity-Verlet step (Sec. 3.3), a = accel per unit force
+ * (force_to_accel / mass), FP64 state.
+ * f is float[3n], or double[3n] when flags has MD_PAIR_FP64.
+ * MD_KICK_DRIFT: x is not re-wrapped.  If xref is not NULL, status[0] is set
+ *   to `tag` when some atom has |minimg(x - xref)|^2 > half_skin_sq (the
+ *   rebuild rule: moved more than half the skin since the last build);
+ *   status[1] gets bit 0 set when a new position is not finite.  status is
+ *   never cleared by the library.  If xs is not NULL, the scaled
+ *   coordinates are rewritten from the new positions (xs[4i+3] untouched).
+ * MD_KICK: if ke is not NULL, *ke (device) = 1/2 mass sum |v|^2 over the
+ *   updated velocities, reduced in FP64 in a fixed order. */
+int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x,
+                 double *v, const void *f, double dt, double accel,
+                 double mass, const double *xref, double half_skin_sq,
+                 int32_t *status, int32_t tag, uint32_t *xs, double *ke,
+                 int32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MD_H */

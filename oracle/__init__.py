@@ -21,7 +21,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         srcs = [os.path.join(_HERE, s) for s in _SOURCES
                 if os.path.exists(os.path.join(_HERE, s))]
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
                "-fopenmp", *srcs, "-o", _LIB_PATH + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
@@ -78,7 +78,7 @@ def _declare(L):
     L.or_forces_eam.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
                                 C.POINTER(FSParams), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_md_run.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
-                            C.POINTER(MDParams), C.c_int64, _dp, _dp]
+                            C.POINTER(MDParams), C.c_int64, _dp, _dp, _dp]
     L.or_md_run.restype = C.c_int64
     if hasattr(L, "or_mlp_descriptors"):
         _declare_mlp(L)
@@ -175,7 +175,8 @@ def forces_eam(x, L, off, idx, fs: dict):
 
 def md_run(x, v, L, steps, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None,
            r_list, skin, dt, mass=1.0, force_to_accel=1.0, reverse_order=False):
-    """Velocity-Verlet run.  Returns dict(x, v, epot[steps+1], ekin[steps+1], builds)."""
+    """Velocity-Verlet run.  Returns dict(x, v, epot[steps+1], ekin[steps+1],
+    builds, loop_seconds)."""
     xs = _soa(x)
     vs = _soa(v)
     n = len(xs[0])
@@ -189,11 +190,13 @@ def md_run(x, v, L, steps, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None,
     prm.reverse_order = 1 if reverse_order else 0
     ep = np.zeros(steps + 1)
     ek = np.zeros(steps + 1)
+    secs = np.zeros(1)
     builds = lib().or_md_run(n, _p(_box(L)), *[_p(c) for c in xs], *[_p(c) for c in vs],
-                             C.byref(prm), int(steps), _p(ep), _p(ek))
+                             C.byref(prm), int(steps), _p(ep), _p(ek), _p(secs))
     if builds < 0:
         raise MemoryError("oracle md_run failed to allocate")
-    return dict(x=np.stack(xs, 1), v=np.stack(vs, 1), epot=ep, ekin=ek, builds=builds)
+    return dict(x=np.stack(xs, 1), v=np.stack(vs, 1), epot=ep, ekin=ek, builds=builds,
+                loop_seconds=float(secs[0]))
 
 
 def _declare_mlp(L):  # filled in by the MLP part of the oracle

@@ -14,6 +14,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <time.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -366,7 +367,7 @@ static double kinetic(int64_t n, const double *vx, const double *vy,
 int64_t or_md_run(int64_t n, const double L[3], double *x, double *y,
                   double *z, double *vx, double *vy, double *vz,
                   const or_md_params_t *p, int64_t steps, double *epot,
-                  double *ekin)
+                  double *ekin, double *loop_seconds)
 {
     size_t nb = sizeof(double) * (size_t)(n > 0 ? n : 1);
     double *fx = malloc(nb), *fy = malloc(nb), *fz = malloc(nb);
@@ -390,6 +391,8 @@ int64_t or_md_run(int64_t n, const double L[3], double *x, double *y,
     if (epot) epot[0] = ep;
     if (ekin) ekin[0] = kinetic(n, vx, vy, vz, p->mass);
 
+    struct timespec t0, t1;
+    clock_gettime(CLOCK_MONOTONIC, &t0);
     for (int64_t s = 1; s <= steps; ++s) {
         double maxd2 = 0.0;
         for (int64_t i = 0; i < n; ++i) {
@@ -414,6 +417,9 @@ int64_t or_md_run(int64_t n, const double L[3], double *x, double *y,
         if (epot) epot[s] = ep;
         if (ekin) ekin[s] = kinetic(n, vx, vy, vz, p->mass);
     }
+    clock_gettime(CLOCK_MONOTONIC, &t1);
+    if (loop_seconds)
+        *loop_seconds = (double)(t1.tv_sec - t0.tv_sec) + 1e-9 * (double)(t1.tv_nsec - t0.tv_nsec);
 out:
     free(fx); free(fy); free(fz); free(xr); free(yr); free(zr);
     free(rho); free(fp); free(l.off); free(l.idx);

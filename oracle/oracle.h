@@ -125,12 +125,15 @@ typedef struct {
  * moved more than skin/2 since the last build, forces, half kick.
  * Per step k (0 = the initial state, k = 1..steps after step k) the arrays
  * epot[k], ekin[k] (may be NULL) receive the potential energy (E_shift for
- * LJ, E_total for EAM) and the kinetic energy.  Returns the number of list
- * builds including the first, or a negative value on allocation failure. */
+ * LJ, E_total for EAM) and the kinetic energy.  If loop_seconds is not
+ * NULL it receives the wall time of the step loop alone (the initial build
+ * and force evaluation excluded, as in the paper's timing, Sec. 3.3).
+ * Returns the number of list builds including the first, or a negative
+ * value on allocation failure. */
 int64_t or_md_run(int64_t n, const double L[3], double *x, double *y,
                   double *z, double *vx, double *vy, double *vz,
                   const or_md_params_t *p, int64_t steps, double *epot,
-                  double *ekin);
+                  double *ekin, double *loop_seconds);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,264 @@
+// C ABI façade of libmd.so: argument checks, workspace layout, Morton
+// tables, and dispatch to the kernel launchers.  See include/md.h.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "md_common.h"
+
+namespace md {
+int bin_cells(const md_grid_t *, int64_t, double *, int32_t *, int32_t *, int32_t *, void *, const WsLayout &,
+              hipStream_t);
+int permute(int64_t, int32_t, const int32_t *, const void *, void *, int32_t, hipStream_t);
+int scale_positions(const md_box_t *, int64_t, const double *, uint32_t *, hipStream_t);
+int build_neighbors(const md_grid_t *, int64_t, const double *, const int32_t *, int64_t *, int32_t *, int64_t,
+                    int64_t *, void *, const WsLayout &, hipStream_t);
+int forces_lj(const md_box_t *, int64_t, const double *, const uint32_t *, const int64_t *, const int32_t *,
+              const md_lj_t *, void *, double *, int32_t, void *, const WsLayout &, hipStream_t);
+int forces_eam(const md_box_t *, int64_t, uint32_t *, const int64_t *, const int32_t *, const md_fs_t *, float *,
+               float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t);
+int integrate(int32_t, const md_box_t *, int64_t, double *, double *, const void *, double, double, double,
+              const double *, double, int32_t *, int32_t, uint32_t *, double *, int32_t, void *, const WsLayout &,
+              hipStream_t);
+}  // namespace md
+
+using namespace md;
+
+namespace {
+
+inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+constexpr int64_t kMaxAtoms = 2147483646;  // int32 atom indices
+
+bool box_ok(const md_box_t *b)
+{
+    if (!b) return false;
+    for (int a = 0; a < 3; ++a)
+        if (!(b->L[a] > 0.0) || !std::isfinite(b->L[a])) return false;
+    return true;
+}
+
+bool grid_ok(const md_grid_t *g)
+{
+    if (!g || g->n_cells <= 0 || (g->reach != 1 && g->reach != 2)) return false;
+    int64_t c = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (g->nc[a] < 1) return false;
+        c *= g->nc[a];
+    }
+    return c == g->n_cells;
+}
+
+// Workspace validation: big enough for (grid, n) and initialised for a grid
+// with the same number of cells.
+int ws_check(const md_grid_t *g, int64_t n, void *ws, size_t bytes, WsLayout &w)
+{
+    if (!ws) return MD_ERR_WORKSPACE;
+    w = ws_layout(g ? g->n_cells : 0, n);
+    if (bytes < w.total) return MD_ERR_WORKSPACE;
+    return MD_OK;
+}
+
+// workspace for the force and kick calls: only the n-dependent prefix
+// (status words and reduction partials) is used
+int ws_check_n(int64_t n, void *ws, size_t bytes, WsLayout &w)
+{
+    if (!ws) return MD_ERR_WORKSPACE;
+    w = ws_layout(0, n);
+    if (bytes < w.lin2rank) return MD_ERR_WORKSPACE;
+    return MD_OK;
+}
+
+uint64_t spread3(uint64_t v)
+{
+    uint64_t r = 0;
+    for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+    return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *md_error_string(int status)
+{
+    switch (status) {
+    case MD_OK: return "ok";
+    case MD_ERR_ARG: return "invalid argument";
+    case MD_ERR_BOX: return "box too small for the list cutoff (need 0 < r_list < L/2 on every axis)";
+    case MD_ERR_CAPACITY: return "neighbour list exceeds its buffer; reallocate to *needed and retry";
+    case MD_ERR_NONFINITE: return "non-finite position detected";
+    case MD_ERR_HIP: return "HIP runtime error";
+    case MD_ERR_WORKSPACE: return "workspace too small or not initialised";
+    default: return "unknown status";
+    }
+}
+
+int md_grid_init(const md_box_t *box, double r_list, int32_t reach, md_grid_t *grid)
+{
+    if (!box || !grid || (reach != 1 && reach != 2) || !(r_list > 0.0)) return MD_ERR_ARG;
+    if (!box_ok(box)) return MD_ERR_BOX;
+    md_grid_t g{};
+    g.n_cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!(r_list < 0.5 * box->L[a])) return MD_ERR_BOX;
+        g.L[a] = box->L[a];
+        const double nc = std::floor(reach * box->L[a] / r_list);
+        if (nc < 1.0 || nc > 1048576.0) return MD_ERR_BOX;
+        g.nc[a] = int32_t(nc);
+        g.inv_cell[a] = double(g.nc[a]) / box->L[a];
+        g.n_cells *= g.nc[a];
+    }
+    if (g.n_cells > 2147483647) return MD_ERR_BOX;
+    g.r_list = r_list;
+    g.reach = reach;
+    *grid = g;
+    return MD_OK;
+}
+
+int md_grid_cell_ranks(const md_grid_t *grid, int32_t *rank)
+{
+    if (!grid_ok(grid) || !rank) return MD_ERR_ARG;
+    // walk the Morton codes of the enclosing power-of-two cube in order and
+    // number the codes that fall inside the grid
+    int32_t p = 1;
+    const int32_t mx = std::max(grid->nc[0], std::max(grid->nc[1], grid->nc[2]));
+    while (p < mx) p <<= 1;
+    const int64_t nc0 = grid->nc[0], nc1 = grid->nc[1];
+    if (int64_t(p) * p * p <= 4 * grid->n_cells + 4096) {
+        int32_t r = 0;
+        const uint64_t ncode = uint64_t(p) * p * p;
+        for (uint64_t code = 0; code < ncode; ++code) {
+            uint32_t c[3] = {0, 0, 0};
+            for (int b = 0; 3 * b < 63 && (code >> (3 * b)); ++b)
+                for (int a = 0; a < 3; ++a) c[a] |= uint32_t((code >> (3 * b + a)) & 1u) << b;
+            if (int32_t(c[0]) < grid->nc[0] && int32_t(c[1]) < grid->nc[1] && int32_t(c[2]) < grid->nc[2])
+                rank[c[0] + nc0 * (c[1] + nc1 * c[2])] = r++;
+        }
+        return MD_OK;
+    }
+    // elongated grids: sort the codes of the cells
+    std::vector<std::pair<uint64_t, int64_t>> v;
+    v.reserve(size_t(grid->n_cells));
+    for (int64_t z = 0; z < grid->nc[2]; ++z)
+        for (int64_t y = 0; y < nc1; ++y)
+            for (int64_t x = 0; x < nc0; ++x)
+                v.emplace_back(spread3(x) | (spread3(y) << 1) | (spread3(z) << 2), x + nc0 * (y + nc1 * z));
+    std::sort(v.begin(), v.end());
+    for (size_t r = 0; r < v.size(); ++r) rank[v[r].second] = int32_t(r);
+    return MD_OK;
+}
+
+size_t md_workspace_bytes(const md_grid_t *grid, int64_t n)
+{
+    if (!grid_ok(grid) || n < 0 || n > kMaxAtoms) return 0;
+    return ws_layout(grid->n_cells, n).total;
+}
+
+int md_workspace_init(const md_grid_t *grid, int64_t n, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!grid_ok(grid) || n < 0 || n > kMaxAtoms) return MD_ERR_ARG;
+    WsLayout w;
+    if (int rc = ws_check(grid, n, ws, ws_bytes, w)) return rc;
+    std::vector<int32_t> l2r(size_t(grid->n_cells)), r2l(size_t(grid->n_cells));
+    if (int rc = md_grid_cell_ranks(grid, l2r.data())) return rc;
+    for (int64_t l = 0; l < grid->n_cells; ++l) r2l[size_t(l2r[size_t(l)])] = int32_t(l);
+    int32_t hdr[64] = {};
+    hdr[0] = kWsMagic;
+    hdr[1] = int32_t(uint32_t(uint64_t(grid->n_cells) & 0xffffffffu));
+    hdr[2] = int32_t(uint32_t(uint64_t(grid->n_cells) >> 32));
+    hipStream_t s = as_stream(stream);
+    MD_HIP_TRY(hipMemcpyAsync(ws_ptr<char>(ws, w.lin2rank), l2r.data(), l2r.size() * 4, hipMemcpyHostToDevice, s));
+    MD_HIP_TRY(hipMemcpyAsync(ws_ptr<char>(ws, w.rank2lin), r2l.data(), r2l.size() * 4, hipMemcpyHostToDevice, s));
+    MD_HIP_TRY(hipMemcpyAsync(ws_ptr<char>(ws, w.status), hdr, sizeof(hdr), hipMemcpyHostToDevice, s));
+    MD_HIP_TRY(hipStreamSynchronize(s));
+    return MD_OK;
+}
+
+int md_bin_cells(const md_grid_t *grid, int64_t n, double *x, int32_t *cell, int32_t *perm, int32_t *cell_start,
+                 void *ws, size_t ws_bytes, void *stream)
+{
+    if (!grid_ok(grid) || n < 0 || n > kMaxAtoms || !cell_start) return MD_ERR_ARG;
+    if (n > 0 && (!x || !cell || !perm)) return MD_ERR_ARG;
+    WsLayout w;
+    if (int rc = ws_check(grid, n, ws, ws_bytes, w)) return rc;
+    return bin_cells(grid, n, x, cell, perm, cell_start, ws, w, as_stream(stream));
+}
+
+int md_permute(int64_t n, int32_t ncomp, const int32_t *perm, const void *src, void *dst, int32_t elem_bytes,
+               void *stream)
+{
+    if (n < 0 || n > kMaxAtoms || ncomp < 1 || ncomp > 16) return MD_ERR_ARG;
+    if (elem_bytes != 4 && elem_bytes != 8 && elem_bytes != 16) return MD_ERR_ARG;
+    if (n > 0 && (!perm || !src || !dst || src == dst)) return MD_ERR_ARG;
+    return permute(n, ncomp, perm, src, dst, elem_bytes, as_stream(stream));
+}
+
+int md_scale_positions(const md_box_t *box, int64_t n, const double *x, uint32_t *xs, void *stream)
+{
+    if (!box_ok(box)) return MD_ERR_BOX;
+    if (n < 0 || n > kMaxAtoms || (n > 0 && (!x || !xs))) return MD_ERR_ARG;
+    return scale_positions(box, n, x, xs, as_stream(stream));
+}
+
+int md_build_neighbors(const md_grid_t *grid, int64_t n, const double *x, const int32_t *cell_start,
+                       int64_t *offsets, int32_t *idx, int64_t capacity, int64_t *needed, void *ws, size_t ws_bytes,
+                       void *stream)
+{
+    if (!grid_ok(grid) || n < 0 || n > kMaxAtoms || !cell_start || !offsets || !needed || capacity < 0)
+        return MD_ERR_ARG;
+    if (n > 0 && !x) return MD_ERR_ARG;
+    if (capacity > 0 && !idx) return MD_ERR_ARG;
+    WsLayout w;
+    if (int rc = ws_check(grid, n, ws, ws_bytes, w)) return rc;
+    return build_neighbors(grid, n, x, cell_start, offsets, idx, capacity, needed, ws, w, as_stream(stream));
+}
+
+int md_forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *xs, const int64_t *offsets,
+                 const int32_t *idx, const md_lj_t *lj, void *f, double *ev, int32_t flags, void *ws,
+                 size_t ws_bytes, void *stream)
+{
+    if (!box_ok(box)) return MD_ERR_BOX;
+    if (!lj || !(lj->rc > 0.0) || !(lj->sigma > 0.0) || n < 0 || n > kMaxAtoms) return MD_ERR_ARG;
+    if (flags & ~(MD_ENERGY | MD_PAIR_FP64 | MD_NO_COMPENSATE)) return MD_ERR_ARG;
+    if (n > 0 && (!offsets || !idx || !f)) return MD_ERR_ARG;
+    if (n > 0 && (flags & MD_PAIR_FP64) && !x) return MD_ERR_ARG;
+    if (n > 0 && !(flags & MD_PAIR_FP64) && !xs) return MD_ERR_ARG;
+    if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
+    WsLayout w;
+    if (int rc = ws_check_n(n, ws, ws_bytes, w)) return rc;
+    return forces_lj(box, n, x, xs, offsets, idx, lj, f, ev, flags, ws, w, as_stream(stream));
+}
+
+int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, const int64_t *offsets, const int32_t *idx,
+                  const md_fs_t *fs, float *rho, float *fprime, float *f, double *ev, int32_t flags, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    if (!box_ok(box)) return MD_ERR_BOX;
+    if (!fs || !(fs->d > 0.0) || !(fs->c > 0.0) || n < 0 || n > kMaxAtoms) return MD_ERR_ARG;
+    if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE)) return MD_ERR_ARG;
+    if (n > 0 && (!xs || !offsets || !idx || !rho || !fprime || !f)) return MD_ERR_ARG;
+    if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
+    WsLayout w;
+    if (int rc = ws_check_n(n, ws, ws_bytes, w)) return rc;
+    return forces_eam(box, n, xs, offsets, idx, fs, rho, fprime, f, ev, flags, ws, w, as_stream(stream));
+}
+
+int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x, double *v, const void *f, double dt,
+                 double accel, double mass, const double *xref, double half_skin_sq, int32_t *status, int32_t tag,
+                 uint32_t *xs, double *ke, int32_t flags, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!box_ok(box)) return MD_ERR_BOX;
+    if (n < 0 || n > kMaxAtoms || (flags & ~MD_PAIR_FP64)) return MD_ERR_ARG;
+    if (phase != MD_KICK_DRIFT && phase != MD_KICK) return MD_ERR_ARG;
+    if (n > 0 && (!v || !f)) return MD_ERR_ARG;
+    if (phase == MD_KICK_DRIFT && n > 0 && (!x || !status)) return MD_ERR_ARG;
+    WsLayout w{};
+    if (phase == MD_KICK) {
+        if (int rc = ws_check_n(n, ws, ws_bytes, w)) return rc;
+    }
+    return integrate(phase, box, n, x, v, f, dt, accel, mass, xref, half_skin_sq, status, tag, xs, ke, flags, ws, w,
+                     as_stream(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal helpers shared by the HIP translation units of libmd.so.
+// gfx950 only: wave64, 8 XCDs, no portability layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "md.h"
+
+namespace md {
+
+constexpr int kWave = 64;
+constexpr int kXcds = 8;          // MI355X: 8 accelerator complex dies
+constexpr int kBlock = 256;       // threads per block for the streaming kernels
+
+#define MD_HIP_TRY(expr)                                   \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return MD_ERR_HIP;           \
+    } while (0)
+
+// Workgroups are dispatched to the XCDs round-robin (block b runs on XCD
+// b % 8).  Remap so that each XCD processes one contiguous range of logical
+// blocks: with Morton-ordered atoms, neighbours then share that XCD's L2.
+// A bijection on [0, G) for any G.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G)
+{
+    const uint32_t x = b % kXcds, k = b / kXcds, q = G / kXcds, r = G % kXcds;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T v, int width)
+{
+    for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Sum of NV doubles over a block of kBlock threads in a fixed order; the
+// result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds /* NV * kBlock/kWave */)
+{
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] = group_sum(v[c], kWave);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) lds[wave * NV + c] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / kWave; ++w) s += lds[w * NV + c];
+            v[c] = s;
+        }
+    }
+}
+
+// Workspace layout (bytes from the start of ws).  Every region is 256-byte
+// aligned.
+struct WsLayout {
+    size_t status;    // int32[64]: [0] = init magic, [1] = grid n_cells check
+    size_t lin2rank;  // int32[n_cells]
+    size_t rank2lin;  // int32[n_cells]
+    size_t cell_cnt;  // int32[n_cells + 1]
+    size_t slot;      // int32[n]
+    size_t tmp;       // int32[n]
+    size_t nbcnt;     // int32[n]
+    size_t scan;      // int64[scan_blocks]
+    size_t red1;      // double[red_blocks * 8]
+    size_t red2;      // double[red_blocks * 8]
+    size_t total;
+    int64_t red_blocks;
+};
+
+constexpr int kScanItems = 8;                     // per thread
+constexpr int kScanTile = kBlock * kScanItems;    // per block
+constexpr int32_t kWsMagic = 0x4d443535;          // "MD55"
+
+// The regions that depend only on n come first, so the force and kick calls
+// can locate their reduction partials without the cell count.
+inline WsLayout ws_layout(int64_t n_cells, int64_t n)
+{
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    WsLayout w{};
+    size_t o = 0;
+    const int64_t nn = n > 0 ? n : 1;
+    const int64_t m = (n_cells + 1 > nn + 1 ? n_cells + 1 : nn + 1);
+    const int64_t scan_blocks = (m + kScanTile - 1) / kScanTile + 1;
+    w.red_blocks = nn / 16 + 64;
+    w.status = o;   o += up(64 * 4);
+    w.red1 = o;     o += up(size_t(w.red_blocks) * 8 * 8);
+    w.red2 = o;     o += up(size_t(w.red_blocks) * 8 * 8);
+    w.slot = o;     o += up(size_t(nn) * 4);
+    w.tmp = o;      o += up(size_t(nn) * 4);
+    w.nbcnt = o;    o += up(size_t(nn) * 4);
+    w.lin2rank = o; o += up(size_t(n_cells) * 4);
+    w.rank2lin = o; o += up(size_t(n_cells) * 4);
+    w.cell_cnt = o; o += up(size_t(n_cells + 1) * 4);
+    w.scan = o;     o += up(size_t(scan_blocks) * 8);
+    w.total = o;
+    return w;
+}
+
+template <typename T>
+inline T *ws_ptr(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
+
+// ---- launchers implemented in the kernel translation units ----
+int launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s);
+// out[0] = 0, out[k+1] = sum_{q<=k} in[q], k < m.  OutT = int32_t or int64_t.
+int launch_scan_i32_to_i32(const int32_t *in, int32_t *out, int64_t m, int64_t *bsum, hipStream_t s);
+int launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t m, int64_t *bsum, hipStream_t s);
+// out[c] = sum over nb partial rows of part[b*8 + c], fixed order; then the
+// combination selected by `mode` (see md_reduce.hip).
+int launch_reduce_partials(const double *part1, int64_t nb1, const double *part2, int64_t nb2,
+                           double *out, int mode, double a0, double a1, hipStream_t s);
+
+enum ReduceMode { kReduceLJ = 0, kReduceEAM = 1, kReduceKE = 2 };
+
+}  // namespace md

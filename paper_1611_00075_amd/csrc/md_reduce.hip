@@ -1,0 +1,182 @@
+// Device-wide scans, fills and deterministic reductions.
+//
+// The scans turn per-cell atom counts into cell offsets (counting sort) and
+// per-atom neighbour counts into 64-bit list offsets.  Reductions combine
+// per-block FP64 partials in one fixed order, so energies, virials and
+// kinetic energies are bitwise reproducible run to run.
+#include "md_common.h"
+
+namespace md {
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t count, int32_t value)
+{
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+int launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s)
+{
+    if (count <= 0) return MD_OK;
+    const int64_t g = (count + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_fill_i32, dim3(uint32_t(g)), dim3(kBlock), 0, s, p, count, value);
+    MD_HIP_TRY(hipGetLastError());
+    return MD_OK;
+}
+
+// inclusive scan of one int64 per thread over the block (wave shuffles + LDS)
+__device__ __forceinline__ int64_t block_incl_scan(int64_t v, int64_t *lds /* kBlock/kWave */)
+{
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int64_t t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    if (lane == kWave - 1) lds[wave] = v;
+    __syncthreads();
+    int64_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += lds[w];
+    __syncthreads();
+    return v + pre;
+}
+
+// phase 1: sum of each tile of kScanTile inputs
+__global__ __launch_bounds__(kBlock) void k_scan_tile_sums(const int32_t *in, int64_t m, int64_t *bsum)
+{
+    __shared__ int64_t lds[kBlock / kWave];
+    const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t q = base + k;
+        if (q < m) s += in[q];
+    }
+    s = block_incl_scan(s, lds);
+    if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = s;
+}
+
+// phase 2: exclusive scan of the tile sums in place (one block, any count)
+__global__ __launch_bounds__(kBlock) void k_scan_tile_offsets(int64_t *bsum, int64_t nb)
+{
+    __shared__ int64_t lds[kBlock / kWave];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+        const int64_t q = b0 + threadIdx.x;
+        const int64_t v = q < nb ? bsum[q] : 0;
+        const int64_t inc = block_incl_scan(v, lds);
+        const int64_t c = carry;
+        if (q < nb) bsum[q] = c + inc - v;
+        __syncthreads();
+        if (threadIdx.x == kBlock - 1) carry = c + inc;
+        __syncthreads();
+    }
+}
+
+// phase 3: rescan each tile and write out[q+1] = inclusive prefix (out[0] = 0)
+template <typename OutT>
+__global__ __launch_bounds__(kBlock) void k_scan_write(const int32_t *in, int64_t m, const int64_t *bsum, OutT *out)
+{
+    __shared__ int64_t lds[kBlock / kWave];
+    const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+    int32_t v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t q = base + k;
+        v[k] = q < m ? in[q] : 0;
+        s += v[k];
+    }
+    const int64_t inc = block_incl_scan(s, lds);
+    int64_t run = bsum[blockIdx.x] + inc - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t q = base + k;
+        run += v[k];
+        if (q < m) out[q + 1] = OutT(run);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = OutT(0);
+}
+
+template <typename OutT>
+static int scan_impl(const int32_t *in, OutT *out, int64_t m, int64_t *bsum, hipStream_t s)
+{
+    if (m <= 0) {
+        hipLaunchKernelGGL(k_scan_write<OutT>, dim3(1), dim3(kBlock), 0, s, in, int64_t(0), bsum, out);
+        MD_HIP_TRY(hipGetLastError());
+        // bsum[0] may be garbage but no item reads it except out[0] = 0
+        return MD_OK;
+    }
+    const int64_t nb = (m + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(uint32_t(nb)), dim3(kBlock), 0, s, in, m, bsum);
+    hipLaunchKernelGGL(k_scan_tile_offsets, dim3(1), dim3(kBlock), 0, s, bsum, nb);
+    hipLaunchKernelGGL(k_scan_write<OutT>, dim3(uint32_t(nb)), dim3(kBlock), 0, s, in, m, bsum, out);
+    MD_HIP_TRY(hipGetLastError());
+    return MD_OK;
+}
+
+int launch_scan_i32_to_i32(const int32_t *in, int32_t *out, int64_t m, int64_t *bsum, hipStream_t s)
+{
+    return scan_impl<int32_t>(in, out, m, bsum, s);
+}
+
+int launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t m, int64_t *bsum, hipStream_t s)
+{
+    return scan_impl<int64_t>(in, out, m, bsum, s);
+}
+
+// Fixed-order reduction of [nb][8] partial rows: thread t sums rows
+// t, t + kBlock, ... in order, then a fixed tree combines the threads.
+__device__ void reduce_rows(const double *part, int64_t nb, double (&acc)[8], double *lds)
+{
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += kBlock)
+        for (int c = 0; c < 8; ++c) acc[c] += part[b * 8 + c];
+    for (int c = 0; c < 8; ++c) lds[c * kBlock + threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int c = 0; c < 8; ++c) lds[c * kBlock + threadIdx.x] += lds[c * kBlock + threadIdx.x + w];
+        __syncthreads();
+    }
+    for (int c = 0; c < 8; ++c) acc[c] = lds[c * kBlock];
+    __syncthreads();
+}
+
+// mode kReduceLJ : rows = [sum e, pair count, w0..w5] over a full list (every
+//                  pair twice): out = [e/2, e/2 - count/2 * a0, w/2]; a0 = Phi(rc)
+// mode kReduceEAM: part1 rows = [E_embed, ...], part2 rows = [sum V, 0, w0..w5]
+//                  out = [E_embed + V/2, E_embed, w/2]
+// mode kReduceKE : rows = [sum v^2, ...]; out[0] = a0 * sum / 2 (a0 = mass)
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(const double *part1, int64_t nb1, const double *part2,
+                                                            int64_t nb2, double *out, int mode, double a0, double a1)
+{
+    __shared__ double lds[8 * kBlock];
+    double r1[8], r2[8];
+    reduce_rows(part1, nb1, r1, lds);
+    if (part2) reduce_rows(part2, nb2, r2, lds);
+    if (threadIdx.x != 0) return;
+    if (mode == kReduceLJ) {
+        out[0] = 0.5 * r1[0];
+        out[1] = 0.5 * r1[0] - 0.5 * r1[1] * a0;
+        for (int c = 2; c < 8; ++c) out[c] = 0.5 * r1[c];
+    } else if (mode == kReduceEAM) {
+        out[0] = r1[0] + 0.5 * r2[0];
+        out[1] = r1[0];
+        for (int c = 2; c < 8; ++c) out[c] = 0.5 * r2[c];
+    } else {
+        out[0] = 0.5 * a0 * r1[0];
+    }
+    (void)a1;
+}
+
+int launch_reduce_partials(const double *part1, int64_t nb1, const double *part2, int64_t nb2, double *out, int mode,
+                           double a0, double a1, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, s, part1, nb1, part2, nb2, out, mode, a0, a1);
+    MD_HIP_TRY(hipGetLastError());
+    return MD_OK;
+}
+
+}  // namespace md

@@ -1,0 +1,220 @@
+"""ctypes binding of libmd.so: the entry points of include/md.h under the
+same names.  Argument marshalling only -- every step of the path runs in the
+HIP kernels.  Device buffers are torch tensors on the current GPU; kernels
+run on torch's current stream.
+
+Raises RuntimeError when libmd.so has not been built: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmd.so")
+
+MD_OK, MD_ERR_ARG, MD_ERR_BOX, MD_ERR_CAPACITY = 0, -1, -2, -3
+MD_ERR_NONFINITE, MD_ERR_HIP, MD_ERR_WORKSPACE = -4, -5, -6
+MD_ENERGY, MD_PAIR_FP64, MD_NO_COMPENSATE = 0x1, 0x2, 0x4
+MD_KICK_DRIFT, MD_KICK = 1, 2
+
+
+class Box(C.Structure):
+    _fields_ = [("L", C.c_double * 3)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("L", C.c_double * 3), ("r_list", C.c_double), ("inv_cell", C.c_double * 3),
+                ("nc", C.c_int32 * 3), ("reach", C.c_int32), ("n_cells", C.c_int64)]
+
+
+class LJ(C.Structure):
+    _fields_ = [("eps", C.c_double), ("sigma", C.c_double), ("rc", C.c_double)]
+
+
+class FS(C.Structure):
+    _fields_ = [("A", C.c_double), ("d", C.c_double), ("c", C.c_double),
+                ("c0", C.c_double), ("c1", C.c_double), ("c2", C.c_double)]
+
+
+class MDError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {error_string(code)} ({code})")
+
+
+_lib = None
+_vp = C.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} missing "
+                               "(run python -m paper_1611_00075_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        L.md_error_string.argtypes = [C.c_int]
+        L.md_error_string.restype = C.c_char_p
+        L.md_grid_init.argtypes = [C.POINTER(Box), C.c_double, C.c_int32, C.POINTER(Grid)]
+        L.md_grid_cell_ranks.argtypes = [C.POINTER(Grid), _vp]
+        L.md_workspace_bytes.argtypes = [C.POINTER(Grid), C.c_int64]
+        L.md_workspace_bytes.restype = C.c_size_t
+        L.md_workspace_init.argtypes = [C.POINTER(Grid), C.c_int64, _vp, C.c_size_t, _vp]
+        L.md_bin_cells.argtypes = [C.POINTER(Grid), C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]
+        L.md_permute.argtypes = [C.c_int64, C.c_int32, _vp, _vp, _vp, C.c_int32, _vp]
+        L.md_scale_positions.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, _vp]
+        L.md_build_neighbors.argtypes = [C.POINTER(Grid), C.c_int64, _vp, _vp, _vp, _vp, C.c_int64,
+                                         C.POINTER(C.c_int64), _vp, C.c_size_t, _vp]
+        L.md_forces_lj.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, _vp, _vp, C.POINTER(LJ), _vp,
+                                   _vp, C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_forces_eam.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, _vp, C.POINTER(FS), _vp, _vp,
+                                    _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_integrate.argtypes = [C.c_int32, C.POINTER(Box), C.c_int64, _vp, _vp, _vp, C.c_double,
+                                   C.c_double, C.c_double, _vp, C.c_double, _vp, C.c_int32, _vp, _vp,
+                                   C.c_int32, _vp, C.c_size_t, _vp]
+        _lib = L
+    return _lib
+
+
+def error_string(code: int) -> str:
+    return lib().md_error_string(int(code)).decode()
+
+
+def _check(rc: int, where: str, allow=()):
+    if rc != MD_OK and rc not in allow:
+        raise MDError(rc, where)
+    return rc
+
+
+def _ptr(t, dtype=None, numel=None, name="buffer"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} needs {numel} elements, has {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def box(L) -> Box:
+    b = Box()
+    for a in range(3):
+        b.L[a] = float(L[a])
+    return b
+
+
+# --------------------------------------------------------------------------
+# entry points
+# --------------------------------------------------------------------------
+
+def md_grid_init(L, r_list: float, reach: int = 1) -> Grid:
+    g = Grid()
+    _check(lib().md_grid_init(C.byref(box(L)), float(r_list), int(reach), C.byref(g)), "md_grid_init")
+    return g
+
+
+def md_grid_cell_ranks(grid: Grid) -> np.ndarray:
+    r = np.empty(grid.n_cells, np.int32)
+    _check(lib().md_grid_cell_ranks(C.byref(grid), r.ctypes.data_as(C.c_void_p)), "md_grid_cell_ranks")
+    return r
+
+
+def md_workspace_bytes(grid: Grid, n: int) -> int:
+    b = lib().md_workspace_bytes(C.byref(grid), int(n))
+    if b == 0:
+        raise MDError(MD_ERR_ARG, "md_workspace_bytes")
+    return int(b)
+
+
+def md_workspace_init(grid: Grid, n: int, ws, stream=None):
+    _check(lib().md_workspace_init(C.byref(grid), int(n), _ptr(ws, name="ws"), ws.numel(),
+                                   _stream(stream)), "md_workspace_init")
+
+
+def md_bin_cells(grid: Grid, n: int, x, cell, perm, cell_start, ws, stream=None):
+    import torch
+    _check(lib().md_bin_cells(C.byref(grid), int(n), _ptr(x, torch.float64, 3 * n, "x"),
+                              _ptr(cell, torch.int32, n, "cell"), _ptr(perm, torch.int32, n, "perm"),
+                              _ptr(cell_start, torch.int32, grid.n_cells + 1, "cell_start"),
+                              _ptr(ws, name="ws"), ws.numel(), _stream(stream)), "md_bin_cells")
+
+
+def md_permute(n: int, ncomp: int, perm, src, dst, elem_bytes: int, stream=None):
+    import torch
+    need = ncomp * n * elem_bytes
+    for t, nm in ((src, "src"), (dst, "dst")):
+        if t.numel() * t.element_size() < need:
+            raise ValueError(f"{nm} holds fewer than {need} bytes")
+    _check(lib().md_permute(int(n), int(ncomp), _ptr(perm, torch.int32, n, "perm"),
+                            _ptr(src, name="src"), _ptr(dst, name="dst"), int(elem_bytes),
+                            _stream(stream)), "md_permute")
+
+
+def md_scale_positions(L, n: int, x, xs, stream=None):
+    import torch
+    _check(lib().md_scale_positions(C.byref(box(L)), int(n), _ptr(x, torch.float64, 3 * n, "x"),
+                                    _ptr(xs, torch.int32, 4 * n, "xs"), _stream(stream)),
+           "md_scale_positions")
+
+
+def md_build_neighbors(grid: Grid, n: int, x, cell_start, offsets, idx, ws, stream=None) -> tuple[int, int]:
+    """Returns (status, needed): status is MD_OK or MD_ERR_CAPACITY."""
+    import torch
+    needed = C.c_int64(0)
+    cap = idx.numel() if idx is not None else 0
+    rc = lib().md_build_neighbors(C.byref(grid), int(n), _ptr(x, torch.float64, 3 * n, "x"),
+                                  _ptr(cell_start, torch.int32, grid.n_cells + 1, "cell_start"),
+                                  _ptr(offsets, torch.int64, n + 1, "offsets"),
+                                  _ptr(idx, torch.int32, None, "idx") if cap > 0 else None, int(cap),
+                                  C.byref(needed), _ptr(ws, name="ws"), ws.numel(), _stream(stream))
+    _check(rc, "md_build_neighbors", allow=(MD_ERR_CAPACITY,))
+    return rc, int(needed.value)
+
+
+def md_forces_lj(L, n: int, x, xs, offsets, idx, lj: tuple, f, ev, flags: int, ws, stream=None):
+    import torch
+    fdt = torch.float64 if flags & MD_PAIR_FP64 else torch.float32
+    p = LJ(*[float(v) for v in lj])
+    _check(lib().md_forces_lj(C.byref(box(L)), int(n), _ptr(x, torch.float64, 3 * n, "x"),
+                              _ptr(xs, torch.int32, 4 * n, "xs"), _ptr(offsets, torch.int64, n + 1, "offsets"),
+                              _ptr(idx, torch.int32, None, "idx"), C.byref(p), _ptr(f, fdt, 3 * n, "f"),
+                              _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
+                              _stream(stream)), "md_forces_lj")
+
+
+def md_forces_eam(L, n: int, xs, offsets, idx, fs: dict, rho, fprime, f, ev, flags: int, ws, stream=None):
+    import torch
+    p = FS(fs["A"], fs["d"], fs["c"], fs["c0"], fs["c1"], fs["c2"])
+    _check(lib().md_forces_eam(C.byref(box(L)), int(n), _ptr(xs, torch.int32, 4 * n, "xs"),
+                               _ptr(offsets, torch.int64, n + 1, "offsets"), _ptr(idx, torch.int32, None, "idx"),
+                               C.byref(p), _ptr(rho, torch.float32, n, "rho"),
+                               _ptr(fprime, torch.float32, n, "fprime"), _ptr(f, torch.float32, 3 * n, "f"),
+                               _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
+                               _stream(stream)), "md_forces_eam")
+
+
+def md_integrate(phase: int, L, n: int, x, v, f, dt: float, accel: float, mass: float, xref,
+                 half_skin_sq: float, status, tag: int, xs, ke, flags: int, ws, stream=None):
+    import torch
+    fdt = torch.float64 if flags & MD_PAIR_FP64 else torch.float32
+    _check(lib().md_integrate(int(phase), C.byref(box(L)), int(n), _ptr(x, torch.float64, 3 * n, "x"),
+                              _ptr(v, torch.float64, 3 * n, "v"), _ptr(f, fdt, 3 * n, "f"), float(dt),
+                              float(accel), float(mass), _ptr(xref, torch.float64, 3 * n, "xref"),
+                              float(half_skin_sq), _ptr(status, torch.int32, 2, "status"), int(tag),
+                              _ptr(xs, torch.int32, 4 * n, "xs"), _ptr(ke, torch.float64, 1, "ke"), int(flags),
+                              _ptr(ws, name="ws"), ws.numel(), _stream(stream)), "md_integrate")

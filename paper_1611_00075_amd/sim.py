@@ -1,0 +1,199 @@
+"""Velocity-Verlet driver over the C ABI: owns the device buffers of one
+system and sequences the library calls of a step (Sec. 3.3 of the paper):
+
+    half kick + drift (+ rebuild check)  -> md_integrate(MD_KICK_DRIFT)
+    if some atom moved > skin/2:            md_bin_cells, md_permute,
+                                            md_scale_positions,
+                                            md_build_neighbors
+    forces                               -> md_forces_lj | md_forces_eam
+    half kick (+ kinetic energy)         -> md_integrate(MD_KICK)
+
+All arithmetic runs in the HIP kernels; this module only allocates torch
+device tensors and reads back the 8-byte status words and scalar energies.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import md as M
+
+
+class Simulation:
+    """One periodic system on one GPU.
+
+    potential: "lj" (params eps, sigma, rc) or "eam" (Finnis-Sinclair dict).
+    Positions and velocities are FP64; forces FP32 (FP64 with pair_fp64).
+    Atoms are kept in cell (Morton) order; `ids` maps back to input order.
+    """
+
+    def __init__(self, L, x, v, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None, skin=0.3,
+                 dt=0.005, mass=1.0, force_to_accel=1.0, reach=1, pair_fp64=False,
+                 compensate=True, device="cuda", list_slack=1.15):
+        self.L = np.asarray(L, dtype=np.float64).reshape(3)
+        x = np.asarray(x, dtype=np.float64)
+        self.n = n = int(x.shape[0])
+        self.potential = potential
+        self.lj = tuple(float(a) for a in lj)
+        self.fs = fs
+        rc = self.lj[2] if potential == "lj" else max(fs["d"], fs["c"])
+        self.rc = rc
+        self.skin = float(skin)
+        self.r_list = rc + self.skin
+        self.dt, self.mass, self.k = float(dt), float(mass), float(force_to_accel)
+        self.accel = self.k / self.mass
+        self.half_skin_sq = 0.25 * self.skin * self.skin
+        self.flags = M.MD_PAIR_FP64 if pair_fp64 else 0
+        if not compensate:
+            self.flags |= M.MD_NO_COMPENSATE
+        if potential == "eam" and pair_fp64:
+            raise ValueError("the EAM path is FP32 only")
+        self.dev = torch.device(device)
+        self.list_slack = float(list_slack)
+        d = self.dev
+        self.grid = M.md_grid_init(self.L, self.r_list, reach)
+        self.x = torch.tensor(np.ascontiguousarray(x.T), dtype=torch.float64, device=d)
+        self.v = torch.tensor(np.ascontiguousarray(np.asarray(v, np.float64).T), dtype=torch.float64, device=d)
+        self._x2 = torch.empty_like(self.x)
+        self._v2 = torch.empty_like(self.v)
+        self.xref = torch.empty_like(self.x)
+        self.ids = torch.arange(n, dtype=torch.int32, device=d)
+        self._ids2 = torch.empty_like(self.ids)
+        self.xs = torch.zeros((max(n, 1), 4), dtype=torch.int32, device=d)
+        fdt = torch.float64 if pair_fp64 else torch.float32
+        self.f = torch.zeros((3, max(n, 1)), dtype=fdt, device=d)
+        self.rho = torch.zeros(max(n, 1), dtype=torch.float32, device=d)
+        self.fprime = torch.zeros(max(n, 1), dtype=torch.float32, device=d)
+        self.cell = torch.empty(max(n, 1), dtype=torch.int32, device=d)
+        self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=d)
+        self.cell_start = torch.empty(self.grid.n_cells + 1, dtype=torch.int32, device=d)
+        self.offsets = torch.zeros(n + 1, dtype=torch.int64, device=d)
+        self.idx = torch.empty(max(64 * n, 1), dtype=torch.int32, device=d)
+        self.ws = torch.empty(M.md_workspace_bytes(self.grid, n), dtype=torch.uint8, device=d)
+        M.md_workspace_init(self.grid, n, self.ws)
+        self.status = torch.zeros(2, dtype=torch.int32, device=d)
+        self.ev = torch.zeros(8, dtype=torch.float64, device=d)
+        self.ke = torch.zeros(1, dtype=torch.float64, device=d)
+        self.n_pairs = 0
+        self.builds = 0
+        self.step_count = 0
+        self._status_host = torch.zeros(2, dtype=torch.int32).pin_memory()
+        # optional per-phase timing: a list that step() appends
+        # (phase, start_event, end_event) to, events recorded on the stream
+        self.events = None
+        self.rebuild()
+        self.compute_forces(energy=False)
+
+    # ------------------------------------------------------------------
+    def rebuild(self):
+        """Wrap, bin and sort the atoms, then build the full lists."""
+        n = self.n
+        M.md_bin_cells(self.grid, n, self.x, self.cell, self.perm, self.cell_start, self.ws)
+        if n > 0:
+            M.md_permute(n, 3, self.perm, self.x, self._x2, 8)
+            M.md_permute(n, 3, self.perm, self.v, self._v2, 8)
+            M.md_permute(n, 1, self.perm, self.ids, self._ids2, 4)
+            self.x, self._x2 = self._x2, self.x
+            self.v, self._v2 = self._v2, self.v
+            self.ids, self._ids2 = self._ids2, self.ids
+        self.xref.copy_(self.x)
+        if not (self.flags & M.MD_PAIR_FP64):
+            M.md_scale_positions(self.L, n, self.x, self.xs)
+        rc, need = M.md_build_neighbors(self.grid, n, self.x, self.cell_start, self.offsets, self.idx, self.ws)
+        if rc == M.MD_ERR_CAPACITY:
+            self.idx = torch.empty(int(need * self.list_slack) + 64, dtype=torch.int32, device=self.dev)
+            rc, need = M.md_build_neighbors(self.grid, n, self.x, self.cell_start, self.offsets, self.idx,
+                                            self.ws)
+        self.n_pairs = need
+        self.builds += 1
+
+    def compute_forces(self, energy: bool = False):
+        fl = self.flags | (M.MD_ENERGY if energy else 0)
+        if self.potential == "lj":
+            M.md_forces_lj(self.L, self.n, self.x, self.xs, self.offsets, self.idx, self.lj, self.f, self.ev,
+                           fl, self.ws)
+        else:
+            M.md_forces_eam(self.L, self.n, self.xs, self.offsets, self.idx, self.fs, self.rho, self.fprime,
+                            self.f, self.ev, fl, self.ws)
+
+    def _mark(self, name):
+        if self.events is None:
+            return None
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        return (name, e)
+
+    def _done(self, m):
+        if m is not None:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record()
+            self.events.append((m[0], m[1], e))
+
+    def step(self, energy: bool = False, kinetic: bool = False) -> bool:
+        """One velocity-Verlet step; returns True when the lists were rebuilt."""
+        self.step_count += 1
+        tag = self.step_count
+        xs = None if self.flags & M.MD_PAIR_FP64 else self.xs
+        m = self._mark("kick_drift")
+        M.md_integrate(M.MD_KICK_DRIFT, self.L, self.n, self.x, self.v, self.f, self.dt, self.accel,
+                       self.mass, self.xref, self.half_skin_sq, self.status, tag, xs, None,
+                       self.flags & M.MD_PAIR_FP64, self.ws)
+        self._done(m)
+        self._status_host.copy_(self.status)          # synchronises with the stream
+        st = self._status_host.tolist()
+        if st[1]:
+            raise M.MDError(M.MD_ERR_NONFINITE, "md_integrate")
+        rebuilt = st[0] == tag
+        if rebuilt:
+            m = self._mark("rebuild")
+            self.rebuild()
+            self._done(m)
+        m = self._mark("forces")
+        self.compute_forces(energy)
+        self._done(m)
+        m = self._mark("kick")
+        M.md_integrate(M.MD_KICK, self.L, self.n, self.x, self.v, self.f, self.dt, self.accel, self.mass,
+                       None, 0.0, None, 0, None, self.ke if kinetic else None, self.flags & M.MD_PAIR_FP64,
+                       self.ws)
+        self._done(m)
+        return rebuilt
+
+    # ------------------------------------------------------------------
+    def energies(self):
+        """(potential, kinetic) of the current state, FP64; potential is
+        E_shift for LJ and E_total for EAM (forces are recomputed)."""
+        self.compute_forces(energy=True)
+        M.md_integrate(M.MD_KICK, self.L, self.n, self.x, self.v, self.f, 0.0, self.accel, self.mass,
+                       None, 0.0, None, 0, None, self.ke, self.flags & M.MD_PAIR_FP64, self.ws)
+        ev = self.ev.cpu().numpy()
+        ke = float(self.ke.cpu()[0])
+        return (ev[1] if self.potential == "lj" else ev[0]), ke
+
+    def by_id(self, t, ncomp=3):
+        """Host copy of a per-atom (ncomp, n) tensor in input order, (n, ncomp)."""
+        ids = self.ids.long()
+        out = torch.empty_like(t[:, : self.n] if t.dim() == 2 else t[: self.n])
+        if t.dim() == 2:
+            out[:, ids] = t[:, : self.n]
+            return out.cpu().numpy().T.copy()
+        out[ids] = t[: self.n]
+        return out.cpu().numpy()
+
+    def positions(self):
+        return self.by_id(self.x)
+
+    def velocities(self):
+        return self.by_id(self.v)
+
+    def forces(self):
+        return self.by_id(self.f)
+
+    def neighbor_sets(self):
+        """Neighbour rows mapped to input ids: list of sorted arrays."""
+        off = self.offsets.cpu().numpy()
+        idx = self.idx[: max(self.n_pairs, 1)].cpu().numpy()[: self.n_pairs]
+        ids = self.ids.cpu().numpy()
+        rows = [None] * self.n
+        for k in range(self.n):
+            rows[ids[k]] = np.sort(ids[idx[off[k]:off[k + 1]]])
+        return rows
