@@ -57,15 +57,16 @@ def run_workload(sim, steps, warmup, torch):
 
 def lj_force_bytes(n_atoms, n_entries):
     """Algorithmic bytes of one LJ force launch: each list entry once (4 B),
-    each atom's scaled position once (16 B), its row offset (8 B) and its
-    force (12 B) once."""
-    return 4 * n_entries + (16 + 8 + 12) * n_atoms
+    each atom's row length (4 B), scaled position (16 B) and force (12 B)
+    once."""
+    return 4 * n_entries + (4 + 16 + 12) * n_atoms
 
 
 def eam_force_bytes(n_atoms, n_entries):
-    """Both EAM passes: list twice, positions twice (16 B), offsets twice,
-    rho + F' written (8 B) and forces written (12 B)."""
-    return 2 * 4 * n_entries + (2 * 16 + 2 * 8 + 8 + 12) * n_atoms
+    """Both EAM passes: list, row lengths and scaled positions read once per
+    pass; rho, F' and the F' word of the scaled coordinates written (12 B);
+    forces written (12 B)."""
+    return 2 * 4 * n_entries + (2 * 4 + 2 * 16 + 12 + 12) * n_atoms
 
 
 def main():

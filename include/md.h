@@ -23,8 +23,7 @@
  *     anything is enqueued; kernel-detected conditions (non-finite
  *     positions) are reported through the status words of md_integrate.
  *   - Calls that share one workspace must not run concurrently.
- *   - Atom counts are limited to n < 2^31 - 1; neighbour-list offsets are
- *     64-bit.
+ *   - Atom counts are limited to n < 2^31 - 1; list positions are 64-bit.
  */
 #ifndef MD_H
 #define MD_H
@@ -79,7 +78,7 @@ typedef struct md_grid {
  * cells of edge >= r_list and the 27-cell stencil; reach = 2 gives cells of
  * edge >= r_list/2 and the 125-cell stencil.  Stencil offsets that coincide
  * modulo nc are visited once.  Returns MD_ERR_BOX unless
- * 0 < r_list < L[a]/2 on every axis. */
+ * 0 < r_list < L[a]/2 and nc[a] <= 1024 on every axis. */
 int md_grid_init(const md_box_t *box, double r_list, int32_t reach,
                  md_grid_t *grid);
 
@@ -130,20 +129,31 @@ int md_scale_positions(const md_box_t *box, int64_t n, const double *x,
 
 /* ---- step a3: neighbour lists ---- */
 
+/* List layout (sliced ELL).  Atoms are grouped in slices of 8 consecutive
+ * (sorted) atoms; row i has capacity row_cap (a multiple of 8) and its
+ * entry e < count[i] <= row_cap is stored at
+ *     idx[(i/8 * row_cap/8 + e/8) * 64 + (i%8) * 8 + e%8],
+ * i.e. the rows of a slice are interleaved in blocks of 8 entries, so idx
+ * holds ceil(n / 8) * 8 * row_cap int32 (sorted atom indices). */
+#define MD_SLICE 8
+
 /* Full Verlet lists (Sec. 3.3): row i holds every j != i with
  * r_ij^2 < r_list^2, r_ij^2 = (dx*dx + dy*dy) + dz*dz of the minimum-image
  * displacement dx = x_j - x_i (shifted by L when |dx| > L/2), in FP64 with
  * no contraction.  j in N(i) iff i in N(j).  Positions must be the wrapped,
  * sorted output of md_bin_cells + md_permute, cell_start its output.
- * Outputs: offsets[n+1] (int64, row i is idx[offsets[i] .. offsets[i+1])),
- * idx[capacity] (sorted atom indices; order within a row is unspecified but
- * deterministic).  Synchronises `stream` once to read the total, stores it
- * in *needed (host) and returns MD_ERR_CAPACITY, without writing idx, when
- * it exceeds `capacity`. */
+ * Outputs: count[n], the rows in idx (order within a row unspecified but
+ * deterministic), and *max_count (device int32) = the longest row.  Rows
+ * longer than row_cap are truncated; the list is then invalid.  If `needed`
+ * (host) is not NULL the call synchronises `stream` once, stores the longest
+ * row there and returns MD_ERR_CAPACITY when it exceeds row_cap (the caller
+ * grows idx and repeats the call); with needed == NULL it does not wait and
+ * the caller must check *max_count before using the list. */
 int md_build_neighbors(const md_grid_t *grid, int64_t n, const double *x,
-                       const int32_t *cell_start, int64_t *offsets,
-                       int32_t *idx, int64_t capacity, int64_t *needed,
-                       void *ws, size_t ws_bytes, void *stream);
+                       const int32_t *cell_start, int32_t row_cap,
+                       int32_t *idx, int32_t *count, int32_t *max_count,
+                       int32_t *needed, void *ws, size_t ws_bytes,
+                       void *stream);
 
 /* ---- step a4: Lennard-Jones ---- */
 
@@ -155,8 +165,9 @@ typedef struct md_lj {
  * every pair visited from both sides so that no force is scattered):
  *   F_i = sum_{j in N(i), r < rc} 24 eps s6 (2 s6 - 1) / r^2 (r_i - r_j),
  *   s6 = (sigma/r)^6, truncated at rc.
+ * The list (row_cap, idx, count) is the output of md_build_neighbors.
  * Default: displacements from the scaled coordinates xs, pair arithmetic in
- * FP32, per-atom sums compensated (Kahan) in FP32 and combined across lanes
+ * FP32, per-lane sums compensated (Kahan) in FP32 and combined across lanes
  * in FP64; f is float[3n].  With MD_PAIR_FP64: displacements from x in
  * FP64 (minimum image as in md_build_neighbors), all arithmetic FP64, f is
  * double[3n]; xs may be NULL.  f is overwritten.
@@ -165,8 +176,8 @@ typedef struct md_lj {
  * W_ab = 1/2 sum_i sum_j f_s R_a R_b in the order xx, yy, zz, xy, xz, yz,
  * reduced in FP64 in a fixed order. */
 int md_forces_lj(const md_box_t *box, int64_t n, const double *x,
-                 const uint32_t *xs, const int64_t *offsets,
-                 const int32_t *idx, const md_lj_t *lj, void *f, double *ev,
+                 const uint32_t *xs, int32_t row_cap, const int32_t *idx,
+                 const int32_t *count, const md_lj_t *lj, void *f, double *ev,
                  int32_t flags, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- steps a5/a6: embedded-atom method ---- */
@@ -186,7 +197,7 @@ typedef struct md_fs {
  * sums.  Outputs: rho[n], fprime[n] (float), f float[3n] (overwritten); with
  * MD_ENERGY, ev[8] = E_total, E_embed, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz. */
 int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs,
-                  const int64_t *offsets, const int32_t *idx,
+                  int32_t row_cap, const int32_t *idx, const int32_t *count,
                   const md_fs_t *fs, float *rho, float *fprime, float *f,
                   double *ev, int32_t flags, void *ws, size_t ws_bytes,
                   void *stream);

@@ -11,12 +11,12 @@ int bin_cells(const md_grid_t *, int64_t, double *, int32_t *, int32_t *, int32_
               hipStream_t);
 int permute(int64_t, int32_t, const int32_t *, const void *, void *, int32_t, hipStream_t);
 int scale_positions(const md_box_t *, int64_t, const double *, uint32_t *, hipStream_t);
-int build_neighbors(const md_grid_t *, int64_t, const double *, const int32_t *, int64_t *, int32_t *, int64_t,
-                    int64_t *, void *, const WsLayout &, hipStream_t);
-int forces_lj(const md_box_t *, int64_t, const double *, const uint32_t *, const int64_t *, const int32_t *,
+int build_neighbors(const md_grid_t *, int64_t, const double *, const int32_t *, int32_t, int32_t *, int32_t *,
+                    int32_t *, int32_t *, void *, const WsLayout &, hipStream_t);
+int forces_lj(const md_box_t *, int64_t, const double *, const uint32_t *, int32_t, const int32_t *, const int32_t *,
               const md_lj_t *, void *, double *, int32_t, void *, const WsLayout &, hipStream_t);
-int forces_eam(const md_box_t *, int64_t, uint32_t *, const int64_t *, const int32_t *, const md_fs_t *, float *,
-               float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t);
+int forces_eam(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, const int32_t *, const md_fs_t *,
+               float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t);
 int integrate(int32_t, const md_box_t *, int64_t, double *, double *, const void *, double, double, double,
               const double *, double, int32_t *, int32_t, uint32_t *, double *, int32_t, void *, const WsLayout &,
               hipStream_t);
@@ -104,7 +104,7 @@ int md_grid_init(const md_box_t *box, double r_list, int32_t reach, md_grid_t *g
         if (!(r_list < 0.5 * box->L[a])) return MD_ERR_BOX;
         g.L[a] = box->L[a];
         const double nc = std::floor(reach * box->L[a] / r_list);
-        if (nc < 1.0 || nc > 1048576.0) return MD_ERR_BOX;
+        if (nc < 1.0 || nc > 1024.0) return MD_ERR_BOX;   // cell coordinates pack into 10 bits
         g.nc[a] = int32_t(nc);
         g.inv_cell[a] = double(g.nc[a]) / box->L[a];
         g.n_cells *= g.nc[a];
@@ -162,7 +162,12 @@ int md_workspace_init(const md_grid_t *grid, int64_t n, void *ws, size_t ws_byte
     if (int rc = ws_check(grid, n, ws, ws_bytes, w)) return rc;
     std::vector<int32_t> l2r(size_t(grid->n_cells)), r2l(size_t(grid->n_cells));
     if (int rc = md_grid_cell_ranks(grid, l2r.data())) return rc;
-    for (int64_t l = 0; l < grid->n_cells; ++l) r2l[size_t(l2r[size_t(l)])] = int32_t(l);
+    // rank -> packed cell coordinates cx | cy << 10 | cz << 20
+    const int64_t nc0 = grid->nc[0], nc1 = grid->nc[1];
+    for (int64_t l = 0; l < grid->n_cells; ++l) {
+        const int32_t cx = int32_t(l % nc0), cy = int32_t((l / nc0) % nc1), cz = int32_t(l / (nc0 * nc1));
+        r2l[size_t(l2r[size_t(l)])] = cx | (cy << 10) | (cz << 20);
+    }
     int32_t hdr[64] = {};
     hdr[0] = kWsMagic;
     hdr[1] = int32_t(uint32_t(uint64_t(grid->n_cells) & 0xffffffffu));
@@ -202,46 +207,47 @@ int md_scale_positions(const md_box_t *box, int64_t n, const double *x, uint32_t
 }
 
 int md_build_neighbors(const md_grid_t *grid, int64_t n, const double *x, const int32_t *cell_start,
-                       int64_t *offsets, int32_t *idx, int64_t capacity, int64_t *needed, void *ws, size_t ws_bytes,
-                       void *stream)
+                       int32_t row_cap, int32_t *idx, int32_t *count, int32_t *max_count, int32_t *needed, void *ws,
+                       size_t ws_bytes, void *stream)
 {
-    if (!grid_ok(grid) || n < 0 || n > kMaxAtoms || !cell_start || !offsets || !needed || capacity < 0)
+    if (!grid_ok(grid) || n < 0 || n > kMaxAtoms || !cell_start || !max_count || row_cap < 1 || row_cap % 8)
         return MD_ERR_ARG;
-    if (n > 0 && !x) return MD_ERR_ARG;
-    if (capacity > 0 && !idx) return MD_ERR_ARG;
+    if (n > 0 && (!x || !idx || !count)) return MD_ERR_ARG;
     WsLayout w;
     if (int rc = ws_check(grid, n, ws, ws_bytes, w)) return rc;
-    return build_neighbors(grid, n, x, cell_start, offsets, idx, capacity, needed, ws, w, as_stream(stream));
+    return build_neighbors(grid, n, x, cell_start, row_cap, idx, count, max_count, needed, ws, w, as_stream(stream));
 }
 
-int md_forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *xs, const int64_t *offsets,
-                 const int32_t *idx, const md_lj_t *lj, void *f, double *ev, int32_t flags, void *ws,
-                 size_t ws_bytes, void *stream)
+int md_forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *xs, int32_t row_cap,
+                 const int32_t *idx, const int32_t *count, const md_lj_t *lj, void *f, double *ev, int32_t flags,
+                 void *ws, size_t ws_bytes, void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
-    if (!lj || !(lj->rc > 0.0) || !(lj->sigma > 0.0) || n < 0 || n > kMaxAtoms) return MD_ERR_ARG;
+    if (!lj || !(lj->rc > 0.0) || !(lj->sigma > 0.0) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8)
+        return MD_ERR_ARG;
     if (flags & ~(MD_ENERGY | MD_PAIR_FP64 | MD_NO_COMPENSATE)) return MD_ERR_ARG;
-    if (n > 0 && (!offsets || !idx || !f)) return MD_ERR_ARG;
+    if (n > 0 && (!idx || !count || !f)) return MD_ERR_ARG;
     if (n > 0 && (flags & MD_PAIR_FP64) && !x) return MD_ERR_ARG;
     if (n > 0 && !(flags & MD_PAIR_FP64) && !xs) return MD_ERR_ARG;
     if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
     WsLayout w;
     if (int rc = ws_check_n(n, ws, ws_bytes, w)) return rc;
-    return forces_lj(box, n, x, xs, offsets, idx, lj, f, ev, flags, ws, w, as_stream(stream));
+    return forces_lj(box, n, x, xs, row_cap, idx, count, lj, f, ev, flags, ws, w, as_stream(stream));
 }
 
-int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, const int64_t *offsets, const int32_t *idx,
-                  const md_fs_t *fs, float *rho, float *fprime, float *f, double *ev, int32_t flags, void *ws,
-                  size_t ws_bytes, void *stream)
+int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t row_cap, const int32_t *idx,
+                  const int32_t *count, const md_fs_t *fs, float *rho, float *fprime, float *f, double *ev,
+                  int32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
-    if (!fs || !(fs->d > 0.0) || !(fs->c > 0.0) || n < 0 || n > kMaxAtoms) return MD_ERR_ARG;
+    if (!fs || !(fs->d > 0.0) || !(fs->c > 0.0) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8)
+        return MD_ERR_ARG;
     if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE)) return MD_ERR_ARG;
-    if (n > 0 && (!xs || !offsets || !idx || !rho || !fprime || !f)) return MD_ERR_ARG;
+    if (n > 0 && (!xs || !idx || !count || !rho || !fprime || !f)) return MD_ERR_ARG;
     if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
     WsLayout w;
     if (int rc = ws_check_n(n, ws, ws_bytes, w)) return rc;
-    return forces_eam(box, n, xs, offsets, idx, fs, rho, fprime, f, ev, flags, ws, w, as_stream(stream));
+    return forces_eam(box, n, xs, row_cap, idx, count, fs, rho, fprime, f, ev, flags, ws, w, as_stream(stream));
 }
 
 int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x, double *v, const void *f, double dt,

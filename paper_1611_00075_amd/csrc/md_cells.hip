@@ -176,8 +176,6 @@ int scale_positions(const md_box_t *box, int64_t n, const double *x, uint32_t *x
 // neighbour lists
 // ---------------------------------------------------------------------------
 
-constexpr int kNbTile = 1024;          // candidates staged in LDS at once
-constexpr int kNbHome = 64;            // home atoms per pass
 constexpr int kMaxStencil = 125;       // (2*reach+1)^3, reach <= 2
 
 // distinct values of (c + o) mod nc, o in [-reach, reach], in increasing o
@@ -185,7 +183,9 @@ __device__ __forceinline__ int stencil_axis(int32_t c, int32_t nc, int32_t reach
 {
     int m = 0;
     for (int o = -reach; o <= reach; ++o) {
-        int32_t v = ((c + o) % nc + nc) % nc;
+        int32_t v = c + o;
+        while (v < 0) v += nc;
+        while (v >= nc) v -= nc;
         bool dup = false;
         for (int k = 0; k < m; ++k) dup |= (out[k] == v);
         if (!dup) out[m++] = v;
@@ -202,109 +202,155 @@ __device__ __forceinline__ double minimg(double d, double L, double hL)
     return d;
 }
 
-// One block per cell (Morton rank).  The atoms of the up to 27 (125)
-// neighbouring cells are contiguous runs of the sorted arrays; they are
-// staged in LDS tiles, and each wave tests one home atom against 64
-// candidates at a time, compacting hits with a ballot.  COUNT writes the row
-// lengths, FILL the rows (candidate order: stencil cell, then sorted index).
-template <bool FILL>
-__global__ __launch_bounds__(kBlock) void k_neighbors(int64_t n, const double *x, GridArgs g, double rl2,
-                                                      const int32_t *cell_start, const int32_t *rank2lin,
-                                                      const int32_t *lin2rank, int32_t *count,
-                                                      const int64_t *offsets, int32_t *idx)
+__device__ __forceinline__ void wave_sync()
 {
-    __shared__ double sx[kNbTile], sy[kNbTile], sz[kNbTile];
-    __shared__ int32_t sj[kNbTile];
-    __shared__ int32_t rstart[kMaxStencil], rbase[kMaxStencil + 1];
-    __shared__ int32_t run[kNbHome];
-    __shared__ int32_t nst;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-    const uint32_t rank = xcd_block(blockIdx.x, gridDim.x);
+constexpr int kNbWaveTile = 128;       // candidates staged per wave at once
+constexpr int kNbWaves = kBlock / kWave;
+
+// Per-wave LDS state.
+struct NbWaveLds {
+    double sx[kNbWaveTile], sy[kNbWaveTile], sz[kNbWaveTile];
+    int32_t sj[kNbWaveTile];
+    int32_t rstart[kMaxStencil], rbase[kMaxStencil + 1];
+};
+
+// One wavefront per cell (Morton rank), four cells per block, no block-wide
+// barriers.  The atoms of the up to 27 (125) neighbouring cells are
+// contiguous runs of the sorted arrays; the wave stages them in LDS tiles of
+// 128 and tests one home atom against 64 candidates at a time, compacting
+// hits with a ballot straight into the sliced-ELL rows (entry e of atom i at
+// idx[(i/8 * row_cap/8 + e/8) * 64 + (i%8) * 8 + e%8]).  Row order: stencil
+// cell, then sorted
+// index.  Rows longer than row_cap are counted but truncated; the longest
+// row length is folded into *max_count.
+//
+// Interior cells (no stencil cell wraps around the box and nc >= 2 reach + 2
+// on every axis) use the plain difference x_j - x_i: every candidate is then
+// closer than half a box, so the minimum-image correction of the definition
+// never applies and the result is bitwise the same.
+__global__ __launch_bounds__(kBlock) void k_neighbors(int64_t n, const double *x, GridArgs g, double rl2,
+                                                      int64_t n_cells, const int32_t *cell_start,
+                                                      const int32_t *rank_xyz, const int32_t *lin2rank,
+                                                      int32_t row_cap, int32_t *idx, int32_t *count,
+                                                      int32_t *max_count)
+{
+    __shared__ NbWaveLds lds_all[kNbWaves];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    NbWaveLds &L = lds_all[wave];
+    const int64_t rank = int64_t(xcd_block(blockIdx.x, gridDim.x)) * kNbWaves + wave;
+    if (rank >= n_cells) return;
     const int32_t h0 = cell_start[rank], h1 = cell_start[rank + 1];
     if (h0 == h1) return;
 
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    if (threadIdx.x == 0) {
-        const int32_t lin = rank2lin[rank];
-        const int32_t cx = lin % g.nc[0], cy = (lin / g.nc[0]) % g.nc[1], cz = lin / (g.nc[0] * g.nc[1]);
-        int32_t ax[5], ay[5], az[5];
-        const int mx = stencil_axis(cx, g.nc[0], g.reach, ax);
-        const int my = stencil_axis(cy, g.nc[1], g.reach, ay);
-        const int mz = stencil_axis(cz, g.nc[2], g.reach, az);
-        int m = 0, base = 0;
-        for (int c = 0; c < mz; ++c)
-            for (int b = 0; b < my; ++b)
-                for (int a = 0; a < mx; ++a) {
-                    const int64_t l = ax[a] + int64_t(g.nc[0]) * (ay[b] + int64_t(g.nc[1]) * az[c]);
-                    const int32_t r = lin2rank[l];
-                    rstart[m] = cell_start[r];
-                    rbase[m] = base;
-                    base += cell_start[r + 1] - cell_start[r];
-                    ++m;
-                }
-        rbase[m] = base;
-        nst = m;
+    // stencil cells: lane t takes cells t and t + 64 (x-fastest order), reads
+    // their ranges, and a shuffle scan forms the range prefix
+    const int32_t pk = rank_xyz[rank];        // packed cell coordinates
+    const int32_t c3[3] = {pk & 1023, (pk >> 10) & 1023, pk >> 20};
+    bool interior = true;
+    for (int a = 0; a < 3; ++a)
+        interior &= (g.nc[a] >= 2 * g.reach + 2) && (c3[a] - g.reach >= 0) && (c3[a] + g.reach < g.nc[a]);
+    int32_t ax[5], ay[5], az[5];
+    const int mx = stencil_axis(c3[0], g.nc[0], g.reach, ax);
+    const int my = stencil_axis(c3[1], g.nc[1], g.reach, ay);
+    const int mz = stencil_axis(c3[2], g.nc[2], g.reach, az);
+    const int m = mx * my * mz;
+    int32_t carry = 0;
+    for (int t0 = 0; t0 < m; t0 += kWave) {
+        const int t = t0 + lane;
+        int32_t len = 0;
+        if (t < m) {
+            // t = a + mx (b + my c) for small mx, my: exact reciprocal multiplies
+            const int q1 = (t * ((65536 + mx - 1) / mx)) >> 16;
+            const int a = t - q1 * mx;
+            const int c = (q1 * ((65536 + my - 1) / my)) >> 16;
+            const int b = q1 - c * my;
+            const int64_t l = ax[a] + int64_t(g.nc[0]) * (ay[b] + int64_t(g.nc[1]) * az[c]);
+            const int32_t r = lin2rank[l];
+            const int32_t st = cell_start[r];
+            len = cell_start[r + 1] - st;
+            L.rstart[t] = st;
+        }
+        int32_t v = len;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int32_t u = __shfl_up(v, o, kWave);
+            if (lane >= o) v += u;
+        }
+        if (t < m) L.rbase[t + 1] = carry + v;
+        carry += __shfl(v, kWave - 1, kWave);
     }
-    __syncthreads();
-    const int m = nst;
-    const int32_t total = rbase[m];
+    if (lane == 0) L.rbase[0] = 0;
+    wave_sync();
+    const int32_t total = carry;
+    int32_t longest = 0;
 
-    for (int32_t hb = h0; hb < h1; hb += kNbHome) {
-        const int32_t hn = min(kNbHome, h1 - hb);
-        if (threadIdx.x < hn) run[threadIdx.x] = 0;
-        __syncthreads();
-        for (int32_t t0 = 0; t0 < total; t0 += kNbTile) {
-            const int32_t tn = min(kNbTile, total - t0);
-            for (int32_t q = threadIdx.x; q < tn; q += kBlock) {
+    for (int32_t hb = h0; hb < h1; hb += kWave) {
+        const int32_t hn = min(kWave, h1 - hb);
+        // home positions, fetched once and broadcast with shuffles
+        const int32_t hl = hb + min(lane, hn - 1);
+        const double xl = x[hl], yl = x[n + hl], zl = x[2 * n + hl];
+        int32_t run_l = 0;                                // row length of home atom `lane`
+        for (int32_t t0 = 0; t0 < total; t0 += kNbWaveTile) {
+            const int32_t tn = min(kNbWaveTile, total - t0);
+            wave_sync();
+            for (int32_t q = lane; q < tn; q += kWave) {
                 const int32_t gq = t0 + q;
                 int lo = 0, hi = m - 1;           // last range with rbase <= gq
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (rbase[mid] <= gq) lo = mid; else hi = mid - 1;
+                    if (L.rbase[mid] <= gq) lo = mid; else hi = mid - 1;
                 }
-                const int32_t j = rstart[lo] + (gq - rbase[lo]);
-                sj[q] = j;
-                sx[q] = x[j];
-                sy[q] = x[n + j];
-                sz[q] = x[2 * n + j];
+                const int32_t j = L.rstart[lo] + (gq - L.rbase[lo]);
+                L.sj[q] = j;
+                L.sx[q] = x[j];
+                L.sy[q] = x[n + j];
+                L.sz[q] = x[2 * n + j];
             }
-            __syncthreads();
-            for (int32_t h = wave; h < hn; h += kBlock / kWave) {
+            wave_sync();
+            for (int32_t h = 0; h < hn; ++h) {
                 const int32_t i = hb + h;
-                const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
-                int32_t r = run[h];
-                const int64_t rowb = FILL ? offsets[i] : 0;
+                const double xi = __shfl(xl, h, kWave), yi = __shfl(yl, h, kWave), zi = __shfl(zl, h, kWave);
+                int32_t r = __builtin_amdgcn_readlane(run_l, h);
+                int32_t *row = idx + (int64_t(i >> 3) * row_cap * 8 + (i & 7) * 8);
                 for (int32_t c0 = 0; c0 < tn; c0 += kWave) {
                     const int32_t q = c0 + lane;
                     bool hit = false;
-                    int32_t j = -1;
                     if (q < tn) {
-                        j = sj[q];
-                        const double dx = minimg(sx[q] - xi, g.L[0], g.hL[0]);
-                        const double dy = minimg(sy[q] - yi, g.L[1], g.hL[1]);
-                        const double dz = minimg(sz[q] - zi, g.L[2], g.hL[2]);
+                        double dx = L.sx[q] - xi, dy = L.sy[q] - yi, dz = L.sz[q] - zi;
+                        if (!interior) {
+                            dx = minimg(dx, g.L[0], g.hL[0]);
+                            dy = minimg(dy, g.L[1], g.hL[1]);
+                            dz = minimg(dz, g.L[2], g.hL[2]);
+                        }
                         const double r2 = (dx * dx + dy * dy) + dz * dz;
-                        hit = (j != i) && (r2 < rl2);
+                        hit = (L.sj[q] != i) && (r2 < rl2);
                     }
                     const uint64_t mask = __ballot(hit);
-                    if (FILL && hit) {
-                        const int pos = __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
-                        idx[rowb + r + pos] = j;
+                    if (hit) {
+                        const int e = r + __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+                        if (e < row_cap) row[int64_t(e >> 3) * 64 + (e & 7)] = L.sj[q];
                     }
                     r += __popcll(mask);
                 }
-                if (lane == 0) run[h] = r;
+                if (lane == h) run_l = r;
             }
-            __syncthreads();
         }
-        if (!FILL && threadIdx.x < hn) count[hb + threadIdx.x] = run[threadIdx.x];
-        __syncthreads();
+        if (lane < hn) count[hb + lane] = run_l;
+        longest = max(longest, lane < hn ? run_l : 0);
     }
+    for (int o = kWave / 2; o > 0; o >>= 1) longest = max(longest, __shfl_xor(longest, o, kWave));
+    if (lane == 0) atomicMax(max_count, longest);
 }
 
-int build_neighbors(const md_grid_t *grid, int64_t n, const double *x, const int32_t *cell_start, int64_t *offsets,
-                    int32_t *idx, int64_t capacity, int64_t *needed, void *ws, const WsLayout &w, hipStream_t s)
+int build_neighbors(const md_grid_t *grid, int64_t n, const double *x, const int32_t *cell_start, int32_t row_cap,
+                    int32_t *idx, int32_t *count, int32_t *max_count, int32_t *needed, void *ws, const WsLayout &w,
+                    hipStream_t s)
 {
     GridArgs g;
     for (int a = 0; a < 3; ++a) {
@@ -315,26 +361,21 @@ int build_neighbors(const md_grid_t *grid, int64_t n, const double *x, const int
     }
     g.reach = grid->reach;
     const double rl2 = grid->r_list * grid->r_list;
-    int32_t *cnt = ws_ptr<int32_t>(ws, w.nbcnt);
-    const uint32_t nb = uint32_t(grid->n_cells);
+    int rc = launch_fill_i32(max_count, 1, 0, s);
+    if (rc) return rc;
+    const uint32_t nb = uint32_t((grid->n_cells + kNbWaves - 1) / kNbWaves);
     if (n > 0) {
-        hipLaunchKernelGGL(k_neighbors<false>, dim3(nb), dim3(kBlock), 0, s, n, x, g, rl2, cell_start,
-                           ws_ptr<int32_t>(ws, w.rank2lin), ws_ptr<int32_t>(ws, w.lin2rank), cnt,
-                           (const int64_t *)nullptr, (int32_t *)nullptr);
+        hipLaunchKernelGGL(k_neighbors, dim3(nb), dim3(kBlock), 0, s, n, x, g, rl2, grid->n_cells, cell_start,
+                           ws_ptr<int32_t>(ws, w.rank2lin), ws_ptr<int32_t>(ws, w.lin2rank), row_cap, idx, count,
+                           max_count);
         MD_HIP_TRY(hipGetLastError());
     }
-    int rc = launch_scan_i32_to_i64(cnt, offsets, n, ws_ptr<int64_t>(ws, w.scan), s);
-    if (rc) return rc;
-    int64_t total = 0;
-    MD_HIP_TRY(hipMemcpyAsync(&total, offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    MD_HIP_TRY(hipStreamSynchronize(s));
-    *needed = total;
-    if (total > capacity) return MD_ERR_CAPACITY;
-    if (n > 0 && total > 0) {
-        hipLaunchKernelGGL(k_neighbors<true>, dim3(nb), dim3(kBlock), 0, s, n, x, g, rl2, cell_start,
-                           ws_ptr<int32_t>(ws, w.rank2lin), ws_ptr<int32_t>(ws, w.lin2rank), (int32_t *)nullptr,
-                           offsets, idx);
-        MD_HIP_TRY(hipGetLastError());
+    if (needed) {
+        int32_t mc = 0;
+        MD_HIP_TRY(hipMemcpyAsync(&mc, max_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        MD_HIP_TRY(hipStreamSynchronize(s));
+        *needed = mc;
+        if (mc > row_cap) return MD_ERR_CAPACITY;
     }
     return MD_OK;
 }

@@ -63,11 +63,10 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds /* NV * k
 struct WsLayout {
     size_t status;    // int32[64]: [0] = init magic, [1] = grid n_cells check
     size_t lin2rank;  // int32[n_cells]
-    size_t rank2lin;  // int32[n_cells]
+    size_t rank2lin;  // int32[n_cells]: packed cell coordinates of each rank
     size_t cell_cnt;  // int32[n_cells + 1]
     size_t slot;      // int32[n]
     size_t tmp;       // int32[n]
-    size_t nbcnt;     // int32[n]
     size_t scan;      // int64[scan_blocks]
     size_t red1;      // double[red_blocks * 8]
     size_t red2;      // double[red_blocks * 8]
@@ -78,6 +77,7 @@ struct WsLayout {
 constexpr int kScanItems = 8;                     // per thread
 constexpr int kScanTile = kBlock * kScanItems;    // per block
 constexpr int32_t kWsMagic = 0x4d443535;          // "MD55"
+constexpr int kSlice = 8;                         // atoms per sliced-ELL slice
 
 // The regions that depend only on n come first, so the force and kick calls
 // can locate their reduction partials without the cell count.
@@ -95,7 +95,6 @@ inline WsLayout ws_layout(int64_t n_cells, int64_t n)
     w.red2 = o;     o += up(size_t(w.red_blocks) * 8 * 8);
     w.slot = o;     o += up(size_t(nn) * 4);
     w.tmp = o;      o += up(size_t(nn) * 4);
-    w.nbcnt = o;    o += up(size_t(nn) * 4);
     w.lin2rank = o; o += up(size_t(n_cells) * 4);
     w.rank2lin = o; o += up(size_t(n_cells) * 4);
     w.cell_cnt = o; o += up(size_t(n_cells + 1) * 4);
@@ -111,7 +110,6 @@ inline T *ws_ptr(void *ws, size_t off) { return reinterpret_cast<T *>(static_cas
 int launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s);
 // out[0] = 0, out[k+1] = sum_{q<=k} in[q], k < m.  OutT = int32_t or int64_t.
 int launch_scan_i32_to_i32(const int32_t *in, int32_t *out, int64_t m, int64_t *bsum, hipStream_t s);
-int launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t m, int64_t *bsum, hipStream_t s);
 // out[c] = sum over nb partial rows of part[b*8 + c], fixed order; then the
 // combination selected by `mode` (see md_reduce.hip).
 int launch_reduce_partials(const double *part1, int64_t nb1, const double *part2, int64_t nb2,

@@ -6,33 +6,28 @@
 // evaluated from both sides and every force is written once by its owner:
 // no atomics and bitwise-reproducible results.
 //
-// Thread mapping: TPA consecutive lanes share one atom and walk its row with
-// stride TPA, so each wave issues coalesced 4*TPA-byte runs of list indices
-// and 16-byte gathers of scaled coordinates.  The TPA partial sums are
-// combined in FP64 with lane shuffles.
+// Lists are sliced ELL: slices of 8 atoms whose rows are interleaved in
+// blocks of 8 entries.  A wave holds one slice, 8 consecutive lanes per atom,
+// so each load of 64 indices reads one contiguous 256-byte run.  Each lane fetches U list entries and then U
+// positions before using any, so U independent gathers per lane are in
+// flight.  The row is walked on a clamped index (the tail re-reads the last
+// entry and masks it out) so the loop has no divergent loads.  The 8
+// partial sums of an atom are combined in FP64 with lane shuffles.
 //
 // FP32 path: displacements come from 32-bit scaled coordinates (fraction of
 // the box times 2^32, Sec. 4.1 "fetch"/"dist"): the integer difference is the
-// periodic minimum image, converted to float and scaled by L/2^32.  Pair
-// arithmetic is FP32; per-lane sums use Kahan compensation.
+// periodic minimum image.  In a cubic box all lengths are kept in units of
+// s = L/2^32 (cutoffs and constants are pre-scaled on the host); the unit
+// vector of a pair does not depend on the unit.  Pair arithmetic is FP32;
+// per-lane sums are Kahan-compensated unless MD_NO_COMPENSATE.
 #include "md_common.h"
 
 namespace md {
 
-struct LJ32 {
-    float sx, sy, sz;      // L / 2^32 per axis
-    float rc2, sig2, eps4, eps24;
-};
-
-struct LJ64 {
-    double L[3], hL[3];
-    double rc2, sig2, eps4, eps24;
-};
-
 template <bool COMP>
-__device__ __forceinline__ void kahan_add(float &s, float &c, float a, float b)
+__device__ __forceinline__ void acc_add(float &s, float &c, float a, float b)
 {
-    // s += a * b with the product's contribution compensated
+    // s += a * b, with the running error of the sum compensated
     if (COMP) {
         const float y = __builtin_fmaf(a, b, -c);
         const float t = s + y;
@@ -43,58 +38,119 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float a, float b)
     }
 }
 
-__device__ __forceinline__ float idiff(uint32_t a, uint32_t b, float scale)
+// Displacement r_i - r_j from scaled coordinates.  CUBIC: in units of
+// L/2^32 (no multiply); otherwise in physical units (ax = L_a / 2^32).
+template <bool CUBIC>
+__device__ __forceinline__ void disp(const uint4 &pi, const uint4 &pj, float ax, float ay, float az, float &dx,
+                                     float &dy, float &dz)
 {
-    return float(int32_t(a - b)) * scale;
+    dx = float(int32_t(pi.x - pj.x));
+    dy = float(int32_t(pi.y - pj.y));
+    dz = float(int32_t(pi.z - pj.z));
+    if (!CUBIC) {
+        dx *= ax;
+        dy *= ay;
+        dz *= az;
+    }
+}
+
+// Sliced-ELL row of atom i: entry e at row[(e / 8) * 64 + e % 8].
+__device__ __forceinline__ const int32_t *ell_row(const int32_t *idx, int64_t i, int32_t cap)
+{
+    return idx + (int64_t(i / kSlice) * cap * kSlice + (i % kSlice) * kSlice);
+}
+
+__device__ __forceinline__ int64_t ell_pos(int32_t e) { return int64_t(e / kSlice) * (kSlice * kSlice) + e % kSlice; }
+
+// Walk row entries [0, cnt) with stride U*TPA starting at `sub`;
+// body(pj, valid).  With lane = 8 * atom + sub the lanes of a wave read one
+// contiguous 256-byte run of the list per load, and each quarter-wave
+// gathers 8 consecutive neighbours of one atom.
+template <int TPA, int U, typename Body>
+__device__ __forceinline__ void walk_row(const uint4 *__restrict__ xs, const int32_t *__restrict__ row, int32_t cnt,
+                                         int sub, Body &&body)
+{
+    for (int32_t t = sub; t < cnt; t += U * TPA) {
+        int32_t j[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = row[ell_pos(min(t + u * TPA, cnt - 1))];
+        uint4 pj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pj[u] = xs[j[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) body(pj[u], t + u * TPA < cnt);
+    }
+}
+
+// The 8 lanes of one atom are consecutive: combine over them in FP64.
+__device__ __forceinline__ double combine(float s, float c)
+{
+    double g = double(s) - double(c);
+#pragma unroll
+    for (int o = 1; o < kSlice; o <<= 1) g += __shfl_xor(g, o, kWave);
+    return g;
+}
+
+// Atom and lane-in-atom of this thread: a wave holds one slice of kSlice
+// atoms, lane = kSlice * a + sub.
+struct SliceLane {
+    int64_t i;
+    int sub;
+};
+
+__device__ __forceinline__ SliceLane slice_lane(uint32_t blk)
+{
+    return {int64_t(blk) * (kBlock / kSlice) + threadIdx.x / kSlice, int(threadIdx.x % kSlice)};
 }
 
 // ---------------------------------------------------------------------------
 // Lennard-Jones, FP32 pair arithmetic
 // ---------------------------------------------------------------------------
-template <int TPA, bool ENERGY, bool COMP>
+struct LJ32 {
+    float ax, ay, az;       // L_a / 2^32 (non-cubic boxes)
+    float len;              // length unit of the displacements (s or 1)
+    float rc2, sig2, eps4, eps24;  // rc^2, sigma^2 in that unit; 4 eps; 24 eps / unit
+};
+
+template <int TPA, int U, bool CUBIC, bool ENERGY, bool COMP>
 __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restrict__ xs,
-                                                 const int64_t *__restrict__ off, const int32_t *__restrict__ idx,
-                                                 LJ32 p, float *__restrict__ f, double *__restrict__ part)
+                                                 int32_t cap, const int32_t *__restrict__ idx,
+                                                 const int32_t *__restrict__ count, LJ32 p, float *__restrict__ f,
+                                                 double *__restrict__ part)
 {
-    constexpr int APB = kBlock / TPA;  // atoms per block
+    static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int sub = threadIdx.x % TPA;
-    const int64_t i = int64_t(blk) * APB + threadIdx.x / TPA;
+    const SliceLane sl = slice_lane(blk);
+    const int64_t i = sl.i;
+    const int sub = sl.sub;
 
     float fx = 0.f, fy = 0.f, fz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     double e = 0.0, np = 0.0, w[6] = {0, 0, 0, 0, 0, 0};
     if (i < n) {
         const uint4 pi = xs[i];
-        const int64_t k1 = off[i + 1];
-        for (int64_t k = off[i] + sub; k < k1; k += TPA) {
-            const uint4 pj = xs[idx[k]];
-            const float dx = idiff(pi.x, pj.x, p.sx);
-            const float dy = idiff(pi.y, pj.y, p.sy);
-            const float dz = idiff(pi.z, pj.z, p.sz);
+        const int32_t cnt = min(count[i], cap);
+        walk_row<TPA, U>(xs, ell_row(idx, i, cap), cnt, sub, [&](const uint4 &pj, bool valid) {
+            float dx, dy, dz;
+            disp<CUBIC>(pi, pj, p.ax, p.ay, p.az, dx, dy, dz);
             const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-            if (r2 < p.rc2) {
-                const float ir2 = __builtin_amdgcn_rcpf(r2);
-                const float s2 = p.sig2 * ir2;
-                const float s6 = s2 * s2 * s2;
-                const float fs = p.eps24 * s6 * __builtin_fmaf(2.f, s6, -1.f) * ir2;
-                kahan_add<COMP>(fx, cx, fs, dx);
-                kahan_add<COMP>(fy, cy, fs, dy);
-                kahan_add<COMP>(fz, cz, fs, dz);
-                if (ENERGY) {
-                    e += double(p.eps4 * (s6 * s6 - s6));
-                    np += 1.0;
-                    w[0] += double(fs * dx * dx); w[1] += double(fs * dy * dy); w[2] += double(fs * dz * dz);
-                    w[3] += double(fs * dx * dy); w[4] += double(fs * dx * dz); w[5] += double(fs * dy * dz);
-                }
+            const bool in = valid && r2 < p.rc2;
+            const float ir2 = __builtin_amdgcn_rcpf(r2);
+            const float s2 = p.sig2 * ir2;
+            const float s6 = s2 * s2 * s2;
+            float fs = p.eps24 * s6 * __builtin_fmaf(2.f, s6, -1.f) * ir2;
+            fs = in ? fs : 0.f;
+            acc_add<COMP>(fx, cx, fs, dx);
+            acc_add<COMP>(fy, cy, fs, dy);
+            acc_add<COMP>(fz, cz, fs, dz);
+            if (ENERGY && in) {
+                e += double(p.eps4 * (s6 * s6 - s6));
+                np += 1.0;
+                w[0] += double(fs * dx * dx); w[1] += double(fs * dy * dy); w[2] += double(fs * dz * dz);
+                w[3] += double(fs * dx * dy); w[4] += double(fs * dx * dz); w[5] += double(fs * dy * dz);
             }
-        }
+        });
     }
-    double gx = double(fx) - double(cx), gy = double(fy) - double(cy), gz = double(fz) - double(cz);
-    if (TPA > 1) {
-        gx = group_sum(gx, TPA);
-        gy = group_sum(gy, TPA);
-        gz = group_sum(gz, TPA);
-    }
+    const double gx = combine(fx, cx), gy = combine(fy, cy), gz = combine(fz, cz);
     if (sub == 0 && i < n) {
         f[i] = float(gx);
         f[n + i] = float(gy);
@@ -102,7 +158,8 @@ __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restr
     }
     if (ENERGY) {
         __shared__ double lds[8 * (kBlock / kWave)];
-        double v[8] = {e, np, w[0], w[1], w[2], w[3], w[4], w[5]};
+        const double u = double(p.len);   // virial back to physical units
+        double v[8] = {e, np, w[0] * u, w[1] * u, w[2] * u, w[3] * u, w[4] * u, w[5] * u};
         block_sum<8>(v, lds);
         if (threadIdx.x == 0)
             for (int c = 0; c < 8; ++c) part[int64_t(blk) * 8 + c] = v[c];
@@ -112,6 +169,11 @@ __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restr
 // ---------------------------------------------------------------------------
 // Lennard-Jones, FP64 pair arithmetic (minimum image as in the list build)
 // ---------------------------------------------------------------------------
+struct LJ64 {
+    double L[3], hL[3];
+    double rc2, sig2, eps4, eps24;
+};
+
 __device__ __forceinline__ double minimg64(double d, double L, double hL)
 {
     if (d > hL)
@@ -123,20 +185,23 @@ __device__ __forceinline__ double minimg64(double d, double L, double hL)
 
 template <int TPA, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_lj64(int64_t n, const double *__restrict__ x,
-                                                 const int64_t *__restrict__ off, const int32_t *__restrict__ idx,
-                                                 LJ64 p, double *__restrict__ f, double *__restrict__ part)
+                                                 int32_t cap, const int32_t *__restrict__ idx,
+                                                 const int32_t *__restrict__ count, LJ64 p, double *__restrict__ f,
+                                                 double *__restrict__ part)
 {
-    constexpr int APB = kBlock / TPA;
+    static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int sub = threadIdx.x % TPA;
-    const int64_t i = int64_t(blk) * APB + threadIdx.x / TPA;
+    const SliceLane sl = slice_lane(blk);
+    const int64_t i = sl.i;
+    const int sub = sl.sub;
 
     double fx = 0, fy = 0, fz = 0, e = 0, np = 0, w[6] = {0, 0, 0, 0, 0, 0};
     if (i < n) {
         const double xi = x[i], yi = x[n + i], zi = x[2 * n + i];
-        const int64_t k1 = off[i + 1];
-        for (int64_t k = off[i] + sub; k < k1; k += TPA) {
-            const int64_t j = idx[k];
+        const int32_t cnt = min(count[i], cap);
+        const int32_t *row = ell_row(idx, i, cap);
+        for (int32_t k = sub; k < cnt; k += TPA) {
+            const int64_t j = row[ell_pos(k)];
             // displacement i -> j as in the plain definition, then R = -d
             const double dx = minimg64(x[j] - xi, p.L[0], p.hL[0]);
             const double dy = minimg64(x[n + j] - yi, p.L[1], p.hL[1]);
@@ -158,10 +223,11 @@ __global__ __launch_bounds__(kBlock) void k_lj64(int64_t n, const double *__rest
             }
         }
     }
-    if (TPA > 1) {
-        fx = group_sum(fx, TPA);
-        fy = group_sum(fy, TPA);
-        fz = group_sum(fz, TPA);
+#pragma unroll
+    for (int o = 1; o < kSlice; o <<= 1) {
+        fx += __shfl_xor(fx, o, kWave);
+        fy += __shfl_xor(fy, o, kWave);
+        fz += __shfl_xor(fz, o, kWave);
     }
     if (sub == 0 && i < n) {
         f[i] = fx;
@@ -184,41 +250,41 @@ __global__ __launch_bounds__(kBlock) void k_lj64(int64_t n, const double *__rest
 // distances (about 65x for the Cu-like set); it is evaluated in powers of
 // t = r - c instead, p0 + p1 t + p2 t^2, with p_k formed on the host in FP64.
 struct FS32 {
-    float sx, sy, sz;
-    float d, d2, c, c2, p0, p1, p2, A;
+    float ax, ay, az;       // L_a / 2^32 (non-cubic boxes)
+    float len;              // length unit of the displacements (s or 1)
+    float d2u, c2u;         // d^2, c^2 in that unit
+    float d, c, p0, p1, p2, A;  // physical
 };
 
 // pass 1: rho_i = sum psi(r_ij), then F_i = -A sqrt(rho_i), F'_i; F'_i is
 // stored in the fourth word of the scaled coordinates for pass 2's gather.
-template <int TPA, bool ENERGY, bool COMP>
+template <int TPA, int U, bool CUBIC, bool ENERGY, bool COMP>
 __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict__ xs,
-                                                    const int64_t *__restrict__ off, const int32_t *__restrict__ idx,
-                                                    FS32 p, float *__restrict__ rho, float *__restrict__ fprime,
+                                                    int32_t cap, const int32_t *__restrict__ idx,
+                                                    const int32_t *__restrict__ count, FS32 p,
+                                                    float *__restrict__ rho, float *__restrict__ fprime,
                                                     double *__restrict__ part)
 {
-    constexpr int APB = kBlock / TPA;
+    static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int sub = threadIdx.x % TPA;
-    const int64_t i = int64_t(blk) * APB + threadIdx.x / TPA;
+    const SliceLane sl = slice_lane(blk);
+    const int64_t i = sl.i;
+    const int sub = sl.sub;
 
     float s = 0.f, c = 0.f;
     if (i < n) {
         const uint4 pi = xs[i];
-        const int64_t k1 = off[i + 1];
-        for (int64_t k = off[i] + sub; k < k1; k += TPA) {
-            const uint4 pj = xs[idx[k]];
-            const float dx = idiff(pi.x, pj.x, p.sx);
-            const float dy = idiff(pi.y, pj.y, p.sy);
-            const float dz = idiff(pi.z, pj.z, p.sz);
+        const int32_t cnt = min(count[i], cap);
+        walk_row<TPA, U>(xs, ell_row(idx, i, cap), cnt, sub, [&](const uint4 &pj, bool valid) {
+            float dx, dy, dz;
+            disp<CUBIC>(pi, pj, p.ax, p.ay, p.az, dx, dy, dz);
             const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-            if (r2 < p.d2) {
-                const float t = __builtin_amdgcn_sqrtf(r2) - p.d;
-                kahan_add<COMP>(s, c, t, t);
-            }
-        }
+            float t = __builtin_amdgcn_sqrtf(r2) * p.len - p.d;
+            t = (valid && r2 < p.d2u) ? t : 0.f;
+            acc_add<COMP>(s, c, t, t);
+        });
     }
-    double g = double(s) - double(c);
-    if (TPA > 1) g = group_sum(g, TPA);
+    const double g = combine(s, c);
     double Fi = 0.0;
     if (sub == 0 && i < n) {
         float F = 0.f, Fp = 0.f;
@@ -245,61 +311,49 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
 }
 
 // pass 2: F_i = -sum_j [(F'_i + F'_j) psi'(r) + V'(r)] (r_i - r_j) / r
-template <int TPA, bool ENERGY, bool COMP>
+template <int TPA, int U, bool CUBIC, bool ENERGY, bool COMP>
 __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__restrict__ xs,
-                                                      const int64_t *__restrict__ off,
-                                                      const int32_t *__restrict__ idx, FS32 p, float *__restrict__ f,
-                                                      double *__restrict__ part)
+                                                      int32_t cap, const int32_t *__restrict__ idx,
+                                                      const int32_t *__restrict__ count, FS32 p,
+                                                      float *__restrict__ f, double *__restrict__ part)
 {
-    constexpr int APB = kBlock / TPA;
+    static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int sub = threadIdx.x % TPA;
-    const int64_t i = int64_t(blk) * APB + threadIdx.x / TPA;
+    const SliceLane sl = slice_lane(blk);
+    const int64_t i = sl.i;
+    const int sub = sl.sub;
 
     float fx = 0.f, fy = 0.f, fz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     double e = 0.0, w[6] = {0, 0, 0, 0, 0, 0};
     if (i < n) {
         const uint4 pi = xs[i];
         const float fpi = __uint_as_float(pi.w);
-        const int64_t k1 = off[i + 1];
-        for (int64_t k = off[i] + sub; k < k1; k += TPA) {
-            const uint4 pj = xs[idx[k]];
-            const float dx = idiff(pi.x, pj.x, p.sx);
-            const float dy = idiff(pi.y, pj.y, p.sy);
-            const float dz = idiff(pi.z, pj.z, p.sz);
+        const int32_t cnt = min(count[i], cap);
+        walk_row<TPA, U>(xs, ell_row(idx, i, cap), cnt, sub, [&](const uint4 &pj, bool valid) {
+            float dx, dy, dz;
+            disp<CUBIC>(pi, pj, p.ax, p.ay, p.az, dx, dy, dz);
             const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-            const bool in_d = r2 < p.d2, in_c = r2 < p.c2;
-            if (in_d || in_c) {
-                const float r = __builtin_amdgcn_sqrtf(r2);
-                const float ir = __builtin_amdgcn_rcpf(r);
-                float dUdr = 0.f;
-                if (in_d) dUdr = (fpi + __uint_as_float(pj.w)) * 2.f * (r - p.d);
-                float V = 0.f;
-                if (in_c) {
-                    const float t = r - p.c;
-                    const float poly = __builtin_fmaf(__builtin_fmaf(p.p2, t, p.p1), t, p.p0);
-                    const float dpoly = __builtin_fmaf(2.f * p.p2, t, p.p1);
-                    dUdr += t * __builtin_fmaf(t, dpoly, 2.f * poly);
-                    V = t * t * poly;
-                }
-                const float g = -dUdr * ir;
-                kahan_add<COMP>(fx, cx, g, dx);
-                kahan_add<COMP>(fy, cy, g, dy);
-                kahan_add<COMP>(fz, cz, g, dz);
-                if (ENERGY) {
-                    e += double(V);
-                    w[0] += double(g * dx * dx); w[1] += double(g * dy * dy); w[2] += double(g * dz * dz);
-                    w[3] += double(g * dx * dy); w[4] += double(g * dx * dz); w[5] += double(g * dy * dz);
-                }
+            const bool in_d = valid && r2 < p.d2u, in_c = valid && r2 < p.c2u;
+            const float ru = __builtin_amdgcn_sqrtf(r2);
+            const float r = ru * p.len;
+            const float dpsi = in_d ? (fpi + __uint_as_float(pj.w)) * 2.f * (r - p.d) : 0.f;
+            const float t = r - p.c;
+            const float poly = __builtin_fmaf(__builtin_fmaf(p.p2, t, p.p1), t, p.p0);
+            const float dpoly = __builtin_fmaf(2.f * p.p2, t, p.p1);
+            const float dV = in_c ? t * __builtin_fmaf(t, dpoly, 2.f * poly) : 0.f;
+            // -(dU/dr) / r in the displacement unit: F = g * (dx, dy, dz)
+            const float g = -(dpsi + dV) * __builtin_amdgcn_rcpf(ru);
+            acc_add<COMP>(fx, cx, g, dx);
+            acc_add<COMP>(fy, cy, g, dy);
+            acc_add<COMP>(fz, cz, g, dz);
+            if (ENERGY && (in_d || in_c)) {
+                if (in_c) e += double(t * t * poly);
+                w[0] += double(g * dx * dx); w[1] += double(g * dy * dy); w[2] += double(g * dz * dz);
+                w[3] += double(g * dx * dy); w[4] += double(g * dx * dz); w[5] += double(g * dy * dz);
             }
-        }
+        });
     }
-    double gx = double(fx) - double(cx), gy = double(fy) - double(cy), gz = double(fz) - double(cz);
-    if (TPA > 1) {
-        gx = group_sum(gx, TPA);
-        gy = group_sum(gy, TPA);
-        gz = group_sum(gz, TPA);
-    }
+    const double gx = combine(fx, cx), gy = combine(fy, cy), gz = combine(fz, cz);
     if (sub == 0 && i < n) {
         f[i] = float(gx);
         f[n + i] = float(gy);
@@ -307,7 +361,8 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
     }
     if (ENERGY) {
         __shared__ double lds[8 * (kBlock / kWave)];
-        double v[8] = {e, 0.0, w[0], w[1], w[2], w[3], w[4], w[5]};
+        const double u = double(p.len);
+        double v[8] = {e, 0.0, w[0] * u, w[1] * u, w[2] * u, w[3] * u, w[4] * u, w[5] * u};
         block_sum<8>(v, lds);
         if (threadIdx.x == 0)
             for (int c = 0; c < 8; ++c) part[int64_t(blk) * 8 + c] = v[c];
@@ -317,25 +372,53 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-constexpr int kTPA = 8;
+constexpr int kTPA = kSlice;   // lanes per atom of the FP32 kernels
+constexpr int kUnroll = 4;
 
 static uint32_t blocks_for(int64_t n, int tpa) { return uint32_t((n * tpa + kBlock - 1) / kBlock); }
 
-int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *xs, const int64_t *off,
-              const int32_t *idx, const md_lj_t *lj, void *f, double *ev, int32_t flags, void *ws,
-              const WsLayout &w, hipStream_t s)
+static bool is_cubic(const md_box_t *b) { return b->L[0] == b->L[1] && b->L[1] == b->L[2]; }
+
+struct List {
+    int32_t cap;
+    const int32_t *idx, *cnt;
+};
+
+template <int TPA, bool CUBIC, bool E, bool C>
+static void launch_lj32(uint32_t gb, hipStream_t s, int64_t n, const uint4 *q, const List &l, const LJ32 &p,
+                        float *f, double *part)
 {
+    hipLaunchKernelGGL((k_lj32<TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx, l.cnt,
+                       p, f, part);
+}
+
+template <int TPA, bool CUBIC>
+static void dispatch_lj32(bool e, bool c, uint32_t gb, hipStream_t s, int64_t n, const uint4 *q, const List &l,
+                          const LJ32 &p, float *f, double *part)
+{
+    if (e && c) launch_lj32<TPA, CUBIC, true, true>(gb, s, n, q, l, p, f, part);
+    else if (e) launch_lj32<TPA, CUBIC, true, false>(gb, s, n, q, l, p, f, part);
+    else if (c) launch_lj32<TPA, CUBIC, false, true>(gb, s, n, q, l, p, f, part);
+    else launch_lj32<TPA, CUBIC, false, false>(gb, s, n, q, l, p, f, part);
+}
+
+int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *xs, int32_t cap, const int32_t *idx,
+              const int32_t *cnt, const md_lj_t *lj, void *f, double *ev, int32_t flags, void *ws, const WsLayout &w,
+              hipStream_t s)
+{
+    const List l{cap, idx, cnt};
     const bool energy = flags & MD_ENERGY;
     double *part = ws_ptr<double>(ws, w.red1);
-    const uint32_t gb = blocks_for(n, kTPA);
-    if (int64_t(gb) > w.red_blocks) return MD_ERR_WORKSPACE;
     const double phi_rc = [&] {
         const double s2 = lj->sigma * lj->sigma / (lj->rc * lj->rc);
         const double s6 = s2 * s2 * s2;
         return 4.0 * lj->eps * (s6 * s6 - s6);
     }();
+    uint32_t gb = 0;
     if (n > 0) {
         if (flags & MD_PAIR_FP64) {
+            gb = blocks_for(n, kTPA);
+            if (int64_t(gb) > w.red_blocks) return MD_ERR_WORKSPACE;
             LJ64 p;
             for (int a = 0; a < 3; ++a) {
                 p.L[a] = box->L[a];
@@ -347,75 +430,92 @@ int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *x
             p.eps24 = 24.0 * lj->eps;
             double *fd = static_cast<double *>(f);
             if (energy)
-                hipLaunchKernelGGL((k_lj64<kTPA, true>), dim3(gb), dim3(kBlock), 0, s, n, x, off, idx, p, fd, part);
+                hipLaunchKernelGGL((k_lj64<kTPA, true>), dim3(gb), dim3(kBlock), 0, s, n, x, cap, idx, cnt, p, fd,
+                                   part);
             else
-                hipLaunchKernelGGL((k_lj64<kTPA, false>), dim3(gb), dim3(kBlock), 0, s, n, x, off, idx, p, fd, part);
+                hipLaunchKernelGGL((k_lj64<kTPA, false>), dim3(gb), dim3(kBlock), 0, s, n, x, cap, idx, cnt, p, fd,
+                                   part);
         } else {
+            const bool cubic = is_cubic(box);
+            gb = blocks_for(n, kTPA);
+            if (int64_t(gb) > w.red_blocks) return MD_ERR_WORKSPACE;
             const double two32 = 4294967296.0;
+            const double u = cubic ? box->L[0] / two32 : 1.0;   // length unit
             LJ32 p;
-            p.sx = float(box->L[0] / two32);
-            p.sy = float(box->L[1] / two32);
-            p.sz = float(box->L[2] / two32);
-            p.rc2 = float(lj->rc * lj->rc);
-            p.sig2 = float(lj->sigma * lj->sigma);
+            p.ax = float(box->L[0] / two32);
+            p.ay = float(box->L[1] / two32);
+            p.az = float(box->L[2] / two32);
+            p.len = float(u);
+            p.rc2 = float(lj->rc * lj->rc / (u * u));
+            p.sig2 = float(lj->sigma * lj->sigma / (u * u));
             p.eps4 = float(4.0 * lj->eps);
-            p.eps24 = float(24.0 * lj->eps);
+            p.eps24 = float(24.0 * lj->eps / u);
             const uint4 *q = reinterpret_cast<const uint4 *>(xs);
             float *ff = static_cast<float *>(f);
             const bool comp = !(flags & MD_NO_COMPENSATE);
-            if (energy && comp)
-                hipLaunchKernelGGL((k_lj32<kTPA, true, true>), dim3(gb), dim3(kBlock), 0, s, n, q, off, idx, p, ff, part);
-            else if (energy)
-                hipLaunchKernelGGL((k_lj32<kTPA, true, false>), dim3(gb), dim3(kBlock), 0, s, n, q, off, idx, p, ff, part);
-            else if (comp)
-                hipLaunchKernelGGL((k_lj32<kTPA, false, true>), dim3(gb), dim3(kBlock), 0, s, n, q, off, idx, p, ff, part);
-            else
-                hipLaunchKernelGGL((k_lj32<kTPA, false, false>), dim3(gb), dim3(kBlock), 0, s, n, q, off, idx, p, ff, part);
+            if (cubic) dispatch_lj32<kTPA, true>(energy, comp, gb, s, n, q, l, p, ff, part);
+            else dispatch_lj32<kTPA, false>(energy, comp, gb, s, n, q, l, p, ff, part);
         }
         MD_HIP_TRY(hipGetLastError());
     }
-    if (energy) return launch_reduce_partials(part, n > 0 ? gb : 0, nullptr, 0, ev, kReduceLJ, phi_rc, 0.0, s);
+    if (energy) return launch_reduce_partials(part, gb, nullptr, 0, ev, kReduceLJ, phi_rc, 0.0, s);
     return MD_OK;
 }
 
-int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, const int64_t *off, const int32_t *idx,
+template <int TPA, bool CUBIC, bool E, bool C>
+static void launch_eam(uint32_t gb, hipStream_t s, int64_t n, uint4 *q, const List &l, const FS32 &p, float *rho,
+                       float *fprime, float *f, double *part1, double *part2)
+{
+    hipLaunchKernelGGL((k_eam_rho<TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx,
+                       l.cnt, p, rho, fprime, part1);
+    hipLaunchKernelGGL((k_eam_force<TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx,
+                       l.cnt, p, f, part2);
+}
+
+template <int TPA, bool CUBIC>
+static void dispatch_eam(bool e, bool c, uint32_t gb, hipStream_t s, int64_t n, uint4 *q, const List &l,
+                         const FS32 &p, float *rho, float *fprime, float *f, double *p1, double *p2)
+{
+    if (e && c) launch_eam<TPA, CUBIC, true, true>(gb, s, n, q, l, p, rho, fprime, f, p1, p2);
+    else if (e) launch_eam<TPA, CUBIC, true, false>(gb, s, n, q, l, p, rho, fprime, f, p1, p2);
+    else if (c) launch_eam<TPA, CUBIC, false, true>(gb, s, n, q, l, p, rho, fprime, f, p1, p2);
+    else launch_eam<TPA, CUBIC, false, false>(gb, s, n, q, l, p, rho, fprime, f, p1, p2);
+}
+
+int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
                const md_fs_t *fs, float *rho, float *fprime, float *f, double *ev, int32_t flags, void *ws,
                const WsLayout &w, hipStream_t s)
 {
+    const List l{cap, idx, cnt};
     const bool energy = flags & MD_ENERGY;
     const bool comp = !(flags & MD_NO_COMPENSATE);
     double *part1 = ws_ptr<double>(ws, w.red1);
     double *part2 = ws_ptr<double>(ws, w.red2);
-    const uint32_t gb = blocks_for(n, kTPA);
+    const bool cubic = is_cubic(box);
+    const uint32_t gb = n > 0 ? blocks_for(n, kTPA) : 0;
     if (int64_t(gb) > w.red_blocks) return MD_ERR_WORKSPACE;
     const double two32 = 4294967296.0;
+    const double u = cubic ? box->L[0] / two32 : 1.0;
     FS32 p;
-    p.sx = float(box->L[0] / two32);
-    p.sy = float(box->L[1] / two32);
-    p.sz = float(box->L[2] / two32);
+    p.ax = float(box->L[0] / two32);
+    p.ay = float(box->L[1] / two32);
+    p.az = float(box->L[2] / two32);
+    p.len = float(u);
+    p.d2u = float(fs->d * fs->d / (u * u));
+    p.c2u = float(fs->c * fs->c / (u * u));
     p.d = float(fs->d);
-    p.d2 = float(fs->d * fs->d);
     p.c = float(fs->c);
-    p.c2 = float(fs->c * fs->c);
     p.p0 = float(fs->c0 + fs->c1 * fs->c + fs->c2 * fs->c * fs->c);
     p.p1 = float(fs->c1 + 2.0 * fs->c2 * fs->c);
     p.p2 = float(fs->c2);
     p.A = float(fs->A);
     uint4 *q = reinterpret_cast<uint4 *>(xs);
     if (n > 0) {
-#define MD_EAM_LAUNCH(E, C)                                                                                   \
-    hipLaunchKernelGGL((k_eam_rho<kTPA, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, off, idx, p, rho, fprime, \
-                       part1);                                                                                \
-    hipLaunchKernelGGL((k_eam_force<kTPA, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, off, idx, p, f, part2)
-        if (energy && comp) { MD_EAM_LAUNCH(true, true); }
-        else if (energy) { MD_EAM_LAUNCH(true, false); }
-        else if (comp) { MD_EAM_LAUNCH(false, true); }
-        else { MD_EAM_LAUNCH(false, false); }
-#undef MD_EAM_LAUNCH
+        if (cubic) dispatch_eam<kTPA, true>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, part1, part2);
+        else dispatch_eam<kTPA, false>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, part1, part2);
         MD_HIP_TRY(hipGetLastError());
     }
-    if (energy)
-        return launch_reduce_partials(part1, n > 0 ? gb : 0, part2, n > 0 ? gb : 0, ev, kReduceEAM, 0.0, 0.0, s);
+    if (energy) return launch_reduce_partials(part1, gb, part2, gb, ev, kReduceEAM, 0.0, 0.0, s);
     return MD_OK;
 }
 

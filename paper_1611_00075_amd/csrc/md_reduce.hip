@@ -1,9 +1,8 @@
 // Device-wide scans, fills and deterministic reductions.
 //
-// The scans turn per-cell atom counts into cell offsets (counting sort) and
-// per-atom neighbour counts into 64-bit list offsets.  Reductions combine
-// per-block FP64 partials in one fixed order, so energies, virials and
-// kinetic energies are bitwise reproducible run to run.
+// The scan turns per-cell atom counts into cell offsets (counting sort).
+// Reductions combine per-block FP64 partials in one fixed order, so energies,
+// virials and kinetic energies are bitwise reproducible run to run.
 #include "md_common.h"
 
 namespace md {
@@ -119,11 +118,6 @@ static int scan_impl(const int32_t *in, OutT *out, int64_t m, int64_t *bsum, hip
 int launch_scan_i32_to_i32(const int32_t *in, int32_t *out, int64_t m, int64_t *bsum, hipStream_t s)
 {
     return scan_impl<int32_t>(in, out, m, bsum, s);
-}
-
-int launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t m, int64_t *bsum, hipStream_t s)
-{
-    return scan_impl<int64_t>(in, out, m, bsum, s);
 }
 
 // Fixed-order reduction of [nb][8] partial rows: thread t sums rows

@@ -20,6 +20,7 @@ MD_OK, MD_ERR_ARG, MD_ERR_BOX, MD_ERR_CAPACITY = 0, -1, -2, -3
 MD_ERR_NONFINITE, MD_ERR_HIP, MD_ERR_WORKSPACE = -4, -5, -6
 MD_ENERGY, MD_PAIR_FP64, MD_NO_COMPENSATE = 0x1, 0x2, 0x4
 MD_KICK_DRIFT, MD_KICK = 1, 2
+MD_SLICE = 8
 
 
 class Box(C.Structure):
@@ -67,12 +68,12 @@ def lib():
         L.md_bin_cells.argtypes = [C.POINTER(Grid), C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]
         L.md_permute.argtypes = [C.c_int64, C.c_int32, _vp, _vp, _vp, C.c_int32, _vp]
         L.md_scale_positions.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, _vp]
-        L.md_build_neighbors.argtypes = [C.POINTER(Grid), C.c_int64, _vp, _vp, _vp, _vp, C.c_int64,
-                                         C.POINTER(C.c_int64), _vp, C.c_size_t, _vp]
-        L.md_forces_lj.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, _vp, _vp, C.POINTER(LJ), _vp,
-                                   _vp, C.c_int32, _vp, C.c_size_t, _vp]
-        L.md_forces_eam.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, _vp, C.POINTER(FS), _vp, _vp,
-                                    _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_build_neighbors.argtypes = [C.POINTER(Grid), C.c_int64, _vp, _vp, C.c_int32, _vp, _vp, _vp,
+                                         C.POINTER(C.c_int32), _vp, C.c_size_t, _vp]
+        L.md_forces_lj.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, C.c_int32, _vp, _vp, C.POINTER(LJ),
+                                   _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_forces_eam.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(FS), _vp,
+                                    _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
         L.md_integrate.argtypes = [C.c_int32, C.POINTER(Box), C.c_int64, _vp, _vp, _vp, C.c_double,
                                    C.c_double, C.c_double, _vp, C.c_double, _vp, C.c_int32, _vp, _vp,
                                    C.c_int32, _vp, C.c_size_t, _vp]
@@ -172,40 +173,55 @@ def md_scale_positions(L, n: int, x, xs, stream=None):
            "md_scale_positions")
 
 
-def md_build_neighbors(grid: Grid, n: int, x, cell_start, offsets, idx, ws, stream=None) -> tuple[int, int]:
-    """Returns (status, needed): status is MD_OK or MD_ERR_CAPACITY."""
+def ell_size(n: int, row_cap: int) -> int:
+    """int32 entries of a sliced-ELL index array for n atoms."""
+    return ((n + MD_SLICE - 1) // MD_SLICE) * MD_SLICE * row_cap
+
+
+def md_build_neighbors(grid: Grid, n: int, x, cell_start, row_cap: int, idx, count, max_count, ws,
+                       sync: bool = True, stream=None) -> tuple[int, int]:
+    """Returns (status, longest row): status MD_OK or MD_ERR_CAPACITY.
+    With sync=False the call does not wait; (MD_OK, -1) is returned and the
+    longest row is left in max_count (device)."""
     import torch
-    needed = C.c_int64(0)
-    cap = idx.numel() if idx is not None else 0
+    needed = C.c_int32(-1)
     rc = lib().md_build_neighbors(C.byref(grid), int(n), _ptr(x, torch.float64, 3 * n, "x"),
-                                  _ptr(cell_start, torch.int32, grid.n_cells + 1, "cell_start"),
-                                  _ptr(offsets, torch.int64, n + 1, "offsets"),
-                                  _ptr(idx, torch.int32, None, "idx") if cap > 0 else None, int(cap),
-                                  C.byref(needed), _ptr(ws, name="ws"), ws.numel(), _stream(stream))
+                                  _ptr(cell_start, torch.int32, grid.n_cells + 1, "cell_start"), int(row_cap),
+                                  _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"),
+                                  _ptr(count, torch.int32, n, "count"), _ptr(max_count, torch.int32, 1, "max_count"),
+                                  C.byref(needed) if sync else None, _ptr(ws, name="ws"), ws.numel(), _stream(stream))
     _check(rc, "md_build_neighbors", allow=(MD_ERR_CAPACITY,))
     return rc, int(needed.value)
 
 
-def md_forces_lj(L, n: int, x, xs, offsets, idx, lj: tuple, f, ev, flags: int, ws, stream=None):
+def md_forces_lj(L, n: int, x, xs, row_cap: int, idx, count, lj: tuple, f, ev, flags: int, ws, stream=None):
     import torch
     fdt = torch.float64 if flags & MD_PAIR_FP64 else torch.float32
     p = LJ(*[float(v) for v in lj])
     _check(lib().md_forces_lj(C.byref(box(L)), int(n), _ptr(x, torch.float64, 3 * n, "x"),
-                              _ptr(xs, torch.int32, 4 * n, "xs"), _ptr(offsets, torch.int64, n + 1, "offsets"),
-                              _ptr(idx, torch.int32, None, "idx"), C.byref(p), _ptr(f, fdt, 3 * n, "f"),
-                              _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
-                              _stream(stream)), "md_forces_lj")
+                              _ptr(xs, torch.int32, 4 * n, "xs"), int(row_cap),
+                              _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"), _ptr(count, torch.int32, n, "count"),
+                              C.byref(p), _ptr(f, fdt, 3 * n, "f"), _ptr(ev, torch.float64, 8, "ev"), int(flags),
+                              _ptr(ws, name="ws"), ws.numel(), _stream(stream)), "md_forces_lj")
 
 
-def md_forces_eam(L, n: int, xs, offsets, idx, fs: dict, rho, fprime, f, ev, flags: int, ws, stream=None):
+def md_forces_eam(L, n: int, xs, row_cap: int, idx, count, fs: dict, rho, fprime, f, ev, flags: int, ws,
+                  stream=None):
     import torch
     p = FS(fs["A"], fs["d"], fs["c"], fs["c0"], fs["c1"], fs["c2"])
-    _check(lib().md_forces_eam(C.byref(box(L)), int(n), _ptr(xs, torch.int32, 4 * n, "xs"),
-                               _ptr(offsets, torch.int64, n + 1, "offsets"), _ptr(idx, torch.int32, None, "idx"),
-                               C.byref(p), _ptr(rho, torch.float32, n, "rho"),
+    _check(lib().md_forces_eam(C.byref(box(L)), int(n), _ptr(xs, torch.int32, 4 * n, "xs"), int(row_cap),
+                               _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"),
+                               _ptr(count, torch.int32, n, "count"), C.byref(p), _ptr(rho, torch.float32, n, "rho"),
                                _ptr(fprime, torch.float32, n, "fprime"), _ptr(f, torch.float32, 3 * n, "f"),
                                _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
                                _stream(stream)), "md_forces_eam")
+
+
+def ell_rows(n: int, row_cap: int, idx, count):
+    """Host view of a sliced-ELL list: list of int arrays (sorted-index rows)."""
+    cnt = count[:n].cpu().numpy()
+    ix = idx[: ell_size(n, row_cap)].cpu().numpy().reshape(-1, row_cap // MD_SLICE, MD_SLICE, MD_SLICE)
+    return [ix[i // MD_SLICE, :, i % MD_SLICE, :].reshape(-1)[: cnt[i]] for i in range(n)]
 
 
 def md_integrate(phase: int, L, n: int, x, v, f, dt: float, accel: float, mass: float, xref,

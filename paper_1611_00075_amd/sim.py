@@ -29,7 +29,7 @@ class Simulation:
 
     def __init__(self, L, x, v, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None, skin=0.3,
                  dt=0.005, mass=1.0, force_to_accel=1.0, reach=1, pair_fp64=False,
-                 compensate=True, device="cuda", list_slack=1.15):
+                 compensate=True, device="cuda", row_cap=None, list_slack=1.2):
         self.L = np.asarray(L, dtype=np.float64).reshape(3)
         x = np.asarray(x, dtype=np.float64)
         self.n = n = int(x.shape[0])
@@ -67,14 +67,17 @@ class Simulation:
         self.cell = torch.empty(max(n, 1), dtype=torch.int32, device=d)
         self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=d)
         self.cell_start = torch.empty(self.grid.n_cells + 1, dtype=torch.int32, device=d)
-        self.offsets = torch.zeros(n + 1, dtype=torch.int64, device=d)
-        self.idx = torch.empty(max(64 * n, 1), dtype=torch.int32, device=d)
+        self.count = torch.zeros(max(n, 1), dtype=torch.int32, device=d)
+        self.max_count = torch.zeros(1, dtype=torch.int32, device=d)
+        # row capacity: the expected neighbour count of a dense region plus slack
+        self.row_cap = (int(row_cap) + 7) // 8 * 8 if row_cap else 64
+        self.idx = torch.empty(max(M.ell_size(n, self.row_cap), 1), dtype=torch.int32, device=d)
         self.ws = torch.empty(M.md_workspace_bytes(self.grid, n), dtype=torch.uint8, device=d)
         M.md_workspace_init(self.grid, n, self.ws)
         self.status = torch.zeros(2, dtype=torch.int32, device=d)
         self.ev = torch.zeros(8, dtype=torch.float64, device=d)
         self.ke = torch.zeros(1, dtype=torch.float64, device=d)
-        self.n_pairs = 0
+        self.longest = 0
         self.builds = 0
         self.step_count = 0
         self._status_host = torch.zeros(2, dtype=torch.int32).pin_memory()
@@ -99,22 +102,29 @@ class Simulation:
         self.xref.copy_(self.x)
         if not (self.flags & M.MD_PAIR_FP64):
             M.md_scale_positions(self.L, n, self.x, self.xs)
-        rc, need = M.md_build_neighbors(self.grid, n, self.x, self.cell_start, self.offsets, self.idx, self.ws)
+        rc, longest = M.md_build_neighbors(self.grid, n, self.x, self.cell_start, self.row_cap, self.idx,
+                                           self.count, self.max_count, self.ws)
         if rc == M.MD_ERR_CAPACITY:
-            self.idx = torch.empty(int(need * self.list_slack) + 64, dtype=torch.int32, device=self.dev)
-            rc, need = M.md_build_neighbors(self.grid, n, self.x, self.cell_start, self.offsets, self.idx,
-                                            self.ws)
-        self.n_pairs = need
+            self.row_cap = (int(longest * self.list_slack) + 4 + 7) // 8 * 8
+            self.idx = torch.empty(max(M.ell_size(n, self.row_cap), 1), dtype=torch.int32, device=self.dev)
+            rc, longest = M.md_build_neighbors(self.grid, n, self.x, self.cell_start, self.row_cap, self.idx,
+                                               self.count, self.max_count, self.ws)
+        self.longest = longest
         self.builds += 1
+
+    @property
+    def n_pairs(self) -> int:
+        """Number of list entries (host sync)."""
+        return int(self.count[: self.n].sum()) if self.n else 0
 
     def compute_forces(self, energy: bool = False):
         fl = self.flags | (M.MD_ENERGY if energy else 0)
         if self.potential == "lj":
-            M.md_forces_lj(self.L, self.n, self.x, self.xs, self.offsets, self.idx, self.lj, self.f, self.ev,
-                           fl, self.ws)
+            M.md_forces_lj(self.L, self.n, self.x, self.xs, self.row_cap, self.idx, self.count, self.lj, self.f,
+                           self.ev, fl, self.ws)
         else:
-            M.md_forces_eam(self.L, self.n, self.xs, self.offsets, self.idx, self.fs, self.rho, self.fprime,
-                            self.f, self.ev, fl, self.ws)
+            M.md_forces_eam(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.fs, self.rho,
+                            self.fprime, self.f, self.ev, fl, self.ws)
 
     def _mark(self, name):
         if self.events is None:
@@ -190,10 +200,9 @@ class Simulation:
 
     def neighbor_sets(self):
         """Neighbour rows mapped to input ids: list of sorted arrays."""
-        off = self.offsets.cpu().numpy()
-        idx = self.idx[: max(self.n_pairs, 1)].cpu().numpy()[: self.n_pairs]
+        r = M.ell_rows(self.n, self.row_cap, self.idx, self.count)
         ids = self.ids.cpu().numpy()
         rows = [None] * self.n
         for k in range(self.n):
-            rows[ids[k]] = np.sort(ids[idx[off[k]:off[k + 1]]])
+            rows[ids[k]] = np.sort(ids[r[k]])
         return rows

@@ -80,26 +80,31 @@ def test_bin_cells_bit_exact(M, orc, name, L, r_list, n, seed, reach):
     assert np.array_equal(cs.cpu().numpy(), np.concatenate([[0], np.cumsum(counts)]))
 
 
-def _gpu_lists(M, x, L, r_list, reach=1):
+def _gpu_lists(M, x, L, r_list, reach=1, row_cap=8):
+    """Bin, sort and build lists on the GPU; rows mapped back to input ids.
+    Starts with a small row capacity to exercise the capacity protocol."""
     n = len(x)
     g, ws, xd, cell, perm, cs = _bin(M, x, L, r_list, reach)
     xs = torch.empty_like(xd)
     M.md_permute(n, 3, perm, xd, xs, 8)
-    off = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
-    idx = torch.empty(1, dtype=torch.int32, device="cuda")
-    rc, need = M.md_build_neighbors(g, n, xs, cs, off, idx, ws)
-    if need > 1:
+    cnt = torch.zeros(max(n, 1), dtype=torch.int32, device="cuda")
+    mx = torch.zeros(1, dtype=torch.int32, device="cuda")
+    idx = torch.empty(max(M.ell_size(n, row_cap), 1), dtype=torch.int32, device="cuda")
+    rc, longest = M.md_build_neighbors(g, n, xs, cs, row_cap, idx, cnt, mx, ws)
+    if longest > row_cap:
         assert rc == M.MD_ERR_CAPACITY
-        idx = torch.empty(need, dtype=torch.int32, device="cuda")
-        rc, need2 = M.md_build_neighbors(g, n, xs, cs, off, idx, ws)
-        assert rc == M.MD_OK and need2 == need
+        row_cap = (longest + 7) // 8 * 8
+        idx = torch.empty(max(M.ell_size(n, row_cap), 1), dtype=torch.int32, device="cuda")
+        rc, longest2 = M.md_build_neighbors(g, n, xs, cs, row_cap, idx, cnt, mx, ws)
+        assert rc == M.MD_OK and longest2 == longest
+    assert int(mx[0]) == longest
     p = perm.cpu().numpy()[:n]
-    o = off.cpu().numpy()
-    ix = idx.cpu().numpy()[:need]
+    r = M.ell_rows(n, row_cap, idx, cnt)
     rows = [None] * n
     for k in range(n):
-        rows[p[k]] = np.sort(p[ix[o[k]:o[k + 1]]])
-    return rows, dict(g=g, ws=ws, x=xs, perm=perm, off=off, idx=idx, need=need)
+        rows[p[k]] = np.sort(p[r[k]])
+    need = int(cnt[:n].sum()) if n else 0
+    return rows, dict(g=g, ws=ws, x=xs, perm=perm, cap=row_cap, idx=idx, cnt=cnt, need=need)
 
 
 @pytest.mark.parametrize("name,L,r_list,n,seed,reach", CASES)
@@ -128,10 +133,11 @@ def test_empty_and_single_atom(M):
         x = np.full((n, 3), 1.5)
         g, ws, xd, cell, perm, cs = _bin(M, x, L, 2.8)
         assert int(cs[-1]) == n
-        off = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
-        idx = torch.empty(1, dtype=torch.int32, device="cuda")
-        rc, need = M.md_build_neighbors(g, n, xd, cs, off, idx, ws)
-        assert rc == M.MD_OK and need == 0
+        cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+        mx = torch.zeros(1, dtype=torch.int32, device="cuda")
+        idx = torch.empty(64, dtype=torch.int32, device="cuda")
+        rc, longest = M.md_build_neighbors(g, n, xd, cs, 8, idx, cnt, mx, ws)
+        assert rc == M.MD_OK and longest == 0
 
 
 def test_abi_rejects_bad_arguments(M):
@@ -199,7 +205,8 @@ def test_forces_lj_fp32_vs_oracle(M, orc, ncell, jit, seed):
     st, xsc = _lj_setup(M, x, s.L)
     f = torch.zeros((3, n), dtype=torch.float32, device="cuda")
     ev = torch.zeros(8, dtype=torch.float64, device="cuda")
-    M.md_forces_lj(s.L, n, st["x"], xsc, st["off"], st["idx"], (1.0, 1.0, 2.5), f, ev, M.MD_ENERGY, st["ws"])
+    M.md_forces_lj(s.L, n, st["x"], xsc, st["cap"], st["idx"], st["cnt"], (1.0, 1.0, 2.5), f, ev, M.MD_ENERGY,
+                   st["ws"])
     p = st["perm"].cpu().numpy()[:n]
     fg = np.empty((n, 3))
     fg[p] = f.cpu().numpy().T.astype(np.float64)
@@ -224,7 +231,7 @@ def test_forces_lj_fp64_vs_oracle(M, orc):
     st, _ = _lj_setup(M, x, s.L)
     f = torch.zeros((3, n), dtype=torch.float64, device="cuda")
     ev = torch.zeros(8, dtype=torch.float64, device="cuda")
-    M.md_forces_lj(s.L, n, st["x"], None, st["off"], st["idx"], (1.0, 1.0, 2.5), f, ev,
+    M.md_forces_lj(s.L, n, st["x"], None, st["cap"], st["idx"], st["cnt"], (1.0, 1.0, 2.5), f, ev,
                    M.MD_ENERGY | M.MD_PAIR_FP64, st["ws"])
     p = st["perm"].cpu().numpy()[:n]
     fg = np.empty((n, 3))
@@ -244,8 +251,8 @@ def test_forces_lj_deterministic(M, orc):
     for _ in range(2):
         f = torch.zeros((3, n), dtype=torch.float32, device="cuda")
         ev = torch.zeros(8, dtype=torch.float64, device="cuda")
-        M.md_forces_lj(s.L, n, st["x"], xsc, st["off"], st["idx"], (1.0, 1.0, 2.5), f, ev, M.MD_ENERGY,
-                       st["ws"])
+        M.md_forces_lj(s.L, n, st["x"], xsc, st["cap"], st["idx"], st["cnt"], (1.0, 1.0, 2.5), f, ev,
+                       M.MD_ENERGY, st["ws"])
         out.append((f.cpu().numpy(), ev.cpu().numpy()))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
@@ -262,7 +269,8 @@ def test_forces_eam_vs_oracle(M, orc):
     rho = torch.zeros(n, dtype=torch.float32, device="cuda")
     fp = torch.zeros(n, dtype=torch.float32, device="cuda")
     ev = torch.zeros(8, dtype=torch.float64, device="cuda")
-    M.md_forces_eam(s.L, n, xsc, st["off"], st["idx"], inputs.FS_CU, rho, fp, f, ev, M.MD_ENERGY, st["ws"])
+    M.md_forces_eam(s.L, n, xsc, st["cap"], st["idx"], st["cnt"], inputs.FS_CU, rho, fp, f, ev, M.MD_ENERGY,
+                    st["ws"])
     p = st["perm"].cpu().numpy()[:n]
     fg = np.empty((n, 3))
     fg[p] = f.cpu().numpy().T
