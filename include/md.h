@@ -224,6 +224,70 @@ int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x,
                  int32_t *status, int32_t tag, uint32_t *xs, double *ke,
                  int32_t flags, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- native step driver ---- */
+
+#define MD_POT_LJ  0
+#define MD_POT_EAM 1
+
+/* One system for md_run.  The caller fills every field (device buffers are
+ * caller-owned; sizes as for the calls above) and keeps the struct between
+ * calls: md_run updates step, builds, phase, need_build, row_cap_needed. */
+typedef struct md_system {
+    md_box_t box;
+    md_grid_t grid;
+    md_lj_t lj;                 /* MD_POT_LJ */
+    md_fs_t fs;                 /* MD_POT_EAM */
+    double dt;
+    double accel;               /* force_to_accel / mass */
+    double half_skin_sq;        /* (skin / 2)^2 */
+    int64_t n;
+    int64_t step;               /* completed steps; step + 1 tags the rebuild check */
+    int64_t builds;             /* list builds so far */
+    double *x, *v, *xref;       /* [3n] FP64 */
+    double *scratch;            /* [3n] permutation scratch */
+    int32_t *ids, *ids_scratch; /* [n]: input index of each sorted atom */
+    uint32_t *xs;               /* [4n] scaled coordinates (FP32 path) */
+    void *f;                    /* float[3n], double[3n] with MD_PAIR_FP64 */
+    float *rho, *fprime;        /* [n], MD_POT_EAM */
+    int32_t *cell, *perm, *cell_start;
+    int32_t *idx, *count, *max_count;   /* sliced-ELL list, row_cap */
+    int32_t *status;            /* device int32[2], zero-initialised */
+    int32_t *host_status;       /* pinned host int32[4] (hipHostMalloc), or NULL */
+    void *ws;
+    size_t ws_bytes;
+    int32_t row_cap;
+    int32_t row_cap_needed;     /* out: set with MD_ERR_CAPACITY */
+    int32_t potential;          /* MD_POT_LJ or MD_POT_EAM */
+    int32_t flags;              /* MD_PAIR_FP64 (LJ only), MD_NO_COMPENSATE */
+    int32_t need_build;         /* 1: build lists (and forces) before stepping */
+    int32_t phase;              /* 0: at a step boundary; 1: a step is in flight */
+    int32_t timing;             /* 1: time each force evaluation with HIP events */
+    int32_t pad_;
+    double force_ms;            /* out (timing): summed force-kernel time */
+    int64_t force_calls;        /* out (timing): force evaluations timed */
+} md_system_t;
+
+/* Runs `steps` velocity-Verlet steps (Sec. 3.3) of the path: kick + drift
+ * with the rebuild check, md_bin_cells + md_permute + md_scale_positions +
+ * md_build_neighbors whenever some atom moved more than skin/2 since the
+ * last build, forces (md_forces_lj or md_forces_eam), kick.  Between two
+ * steps the closing half kick and the next opening half kick are applied as
+ * one kick with the same forces.  On entry with need_build set (a new
+ * system) the lists and forces are built first; otherwise f must hold the
+ * forces of x.  Per-atom arrays stay in the library's sorted order; ids maps
+ * them to input order.
+ * The host waits once per step for the 4-byte rebuild flag: when host_status
+ * is pinned host memory the device publishes the flag there and the host
+ * polls it, otherwise it copies the flag and synchronises the stream.
+ * Returns MD_OK when all steps are done and the state is at a step boundary.
+ * MD_ERR_CAPACITY: a list row exceeded row_cap; row_cap_needed holds the
+ * longest row, a step is in flight (phase 1); grow idx, set row_cap and call
+ * again with the remaining steps (target - step).  MD_ERR_NONFINITE: a
+ * position became non-finite.  With timing set, each force evaluation is
+ * bracketed by HIP events on `stream` and their elapsed times are added to
+ * force_ms / force_calls. */
+int md_run(md_system_t *sys, int64_t steps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

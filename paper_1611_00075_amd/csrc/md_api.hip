@@ -6,22 +6,6 @@
 
 #include "md_common.h"
 
-namespace md {
-int bin_cells(const md_grid_t *, int64_t, double *, int32_t *, int32_t *, int32_t *, void *, const WsLayout &,
-              hipStream_t);
-int permute(int64_t, int32_t, const int32_t *, const void *, void *, int32_t, hipStream_t);
-int scale_positions(const md_box_t *, int64_t, const double *, uint32_t *, hipStream_t);
-int build_neighbors(const md_grid_t *, int64_t, const double *, const int32_t *, int32_t, int32_t *, int32_t *,
-                    int32_t *, int32_t *, void *, const WsLayout &, hipStream_t);
-int forces_lj(const md_box_t *, int64_t, const double *, const uint32_t *, int32_t, const int32_t *, const int32_t *,
-              const md_lj_t *, void *, double *, int32_t, void *, const WsLayout &, hipStream_t);
-int forces_eam(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, const int32_t *, const md_fs_t *,
-               float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t);
-int integrate(int32_t, const md_box_t *, int64_t, double *, double *, const void *, double, double, double,
-              const double *, double, int32_t *, int32_t, uint32_t *, double *, int32_t, void *, const WsLayout &,
-              hipStream_t);
-}  // namespace md
-
 using namespace md;
 
 namespace {
@@ -265,6 +249,30 @@ int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x, doubl
     }
     return integrate(phase, box, n, x, v, f, dt, accel, mass, xref, half_skin_sq, status, tag, xs, ke, flags, ws, w,
                      as_stream(stream));
+}
+
+int md_run(md_system_t *sys, int64_t steps, void *stream)
+{
+    if (!sys || steps < 0 || !box_ok(&sys->box) || !grid_ok(&sys->grid) || sys->n < 0 || sys->n > kMaxAtoms)
+        return MD_ERR_ARG;
+    if (sys->potential != MD_POT_LJ && sys->potential != MD_POT_EAM) return MD_ERR_ARG;
+    if (sys->flags & ~(MD_PAIR_FP64 | MD_NO_COMPENSATE)) return MD_ERR_ARG;
+    if (sys->potential == MD_POT_EAM && (sys->flags & MD_PAIR_FP64)) return MD_ERR_ARG;
+    if (sys->row_cap < 8 || sys->row_cap % 8 || (sys->phase != 0 && sys->phase != 1)) return MD_ERR_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (sys->grid.L[a] != sys->box.L[a]) return MD_ERR_ARG;
+    const bool f64 = sys->flags & MD_PAIR_FP64;
+    if (sys->n > 0) {
+        if (!sys->x || !sys->v || !sys->xref || !sys->scratch || !sys->ids || !sys->ids_scratch || !sys->f ||
+            !sys->cell || !sys->perm || !sys->cell_start || !sys->idx || !sys->count || !sys->max_count ||
+            !sys->status)
+            return MD_ERR_ARG;
+        if (!f64 && !sys->xs) return MD_ERR_ARG;
+        if (sys->potential == MD_POT_EAM && (!sys->rho || !sys->fprime)) return MD_ERR_ARG;
+    }
+    WsLayout w;
+    if (int rc = ws_check(&sys->grid, sys->n, sys->ws, sys->ws_bytes, w)) return rc;
+    return run(sys, steps, as_stream(stream));
 }
 
 }  // extern "C"

@@ -117,4 +117,22 @@ int launch_reduce_partials(const double *part1, int64_t nb1, const double *part2
 
 enum ReduceMode { kReduceLJ = 0, kReduceEAM = 1, kReduceKE = 2 };
 
+// ---- the path's steps (argument checks are done by the C ABI) ----
+int bin_cells(const md_grid_t *, int64_t, double *, int32_t *, int32_t *, int32_t *, void *, const WsLayout &,
+              hipStream_t);
+int permute(int64_t, int32_t, const int32_t *, const void *, void *, int32_t, hipStream_t);
+int scale_positions(const md_box_t *, int64_t, const double *, uint32_t *, hipStream_t);
+int build_neighbors(const md_grid_t *, int64_t, const double *, const int32_t *, int32_t, int32_t *, int32_t *,
+                    int32_t *, int32_t *, void *, const WsLayout &, hipStream_t);
+int forces_lj(const md_box_t *, int64_t, const double *, const uint32_t *, int32_t, const int32_t *, const int32_t *,
+              const md_lj_t *, void *, double *, int32_t, void *, const WsLayout &, hipStream_t);
+int forces_eam(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, const int32_t *, const md_fs_t *,
+               float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t);
+int integrate(int32_t, const md_box_t *, int64_t, double *, double *, const void *, double, double, double,
+              const double *, double, int32_t *, int32_t, uint32_t *, double *, int32_t, void *, const WsLayout &,
+              hipStream_t);
+int run(md_system_t *sys, int64_t steps, hipStream_t s);
+int kick_drift(const md_box_t *box, int64_t n, double *x, double *v, const void *f, bool f64, double kick, double dt,
+               const double *xref, double half_skin_sq, int32_t *status, int32_t tag, uint32_t *xs, hipStream_t s);
+
 }  // namespace md

@@ -1,0 +1,209 @@
+// Native velocity-Verlet driver (Sec. 3.3): runs whole steps of the path
+// without returning to the caller, so no interpreter sits between kernels.
+//
+// Per step: kick + drift with the rebuild check (the closing half kick of the
+// previous step is fused in when steps follow each other), a one-thread
+// kernel publishes the step's rebuild flag into pinned host memory, the host
+// polls that word, rebuilds the lists when some atom has moved more than
+// half the skin, evaluates the forces, and either opens the next step or
+// closes this one with a half kick.
+#include <chrono>
+#include <thread>
+
+#include "md_common.h"
+
+namespace md {
+
+// status[0] == tag: some atom moved more than skin/2 in step `tag`;
+// status[1]: error bits.  Written to host memory last-word-last.
+__global__ void k_publish(const int32_t *status, int32_t *host, int32_t tag)
+{
+    volatile int32_t *h = host;
+    h[1] = status[0] == tag ? 1 : 0;
+    h[2] = status[1];
+    __threadfence_system();
+    h[0] = tag;
+}
+
+namespace {
+
+// Waits for the rebuild flag of step `tag`; returns MD_OK and sets *moved,
+// *bad.  Fast path: the publish kernel writes device-visible pinned memory
+// that the host polls; otherwise a copy and a stream synchronisation.
+int wait_flag(md_system_t *sys, int32_t *host_dev, int32_t tag, hipStream_t s, bool *moved, bool *bad)
+{
+    if (host_dev) {
+        hipLaunchKernelGGL(k_publish, dim3(1), dim3(1), 0, s, sys->status, host_dev, tag);
+        MD_HIP_TRY(hipGetLastError());
+        volatile int32_t *h = sys->host_status;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (uint64_t spin = 0; h[0] != tag; ++spin) {
+            if ((spin & 4095) == 4095) {
+                const hipError_t e = hipStreamQuery(s);
+                if (e != hipSuccess && e != hipErrorNotReady) return MD_ERR_HIP;
+                if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120)) return MD_ERR_HIP;
+                std::this_thread::yield();
+            }
+        }
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        *moved = h[1] != 0;
+        *bad = h[2] != 0;
+        return MD_OK;
+    }
+    int32_t st[2];
+    MD_HIP_TRY(hipMemcpyAsync(st, sys->status, sizeof(st), hipMemcpyDeviceToHost, s));
+    MD_HIP_TRY(hipStreamSynchronize(s));
+    *moved = st[0] == tag;
+    *bad = st[1] != 0;
+    return MD_OK;
+}
+
+int rebuild(md_system_t *sys, const WsLayout &w, hipStream_t s)
+{
+    const int64_t n = sys->n;
+    const size_t b3 = size_t(3 * n) * sizeof(double);
+    int rc = bin_cells(&sys->grid, n, sys->x, sys->cell, sys->perm, sys->cell_start, sys->ws, w, s);
+    if (rc) return rc;
+    if (n > 0) {
+        MD_HIP_TRY(hipMemcpyAsync(sys->scratch, sys->x, b3, hipMemcpyDeviceToDevice, s));
+        if ((rc = permute(n, 3, sys->perm, sys->scratch, sys->x, 8, s))) return rc;
+        MD_HIP_TRY(hipMemcpyAsync(sys->scratch, sys->v, b3, hipMemcpyDeviceToDevice, s));
+        if ((rc = permute(n, 3, sys->perm, sys->scratch, sys->v, 8, s))) return rc;
+        MD_HIP_TRY(hipMemcpyAsync(sys->ids_scratch, sys->ids, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+        if ((rc = permute(n, 1, sys->perm, sys->ids_scratch, sys->ids, 4, s))) return rc;
+        MD_HIP_TRY(hipMemcpyAsync(sys->xref, sys->x, b3, hipMemcpyDeviceToDevice, s));
+        if (!(sys->flags & MD_PAIR_FP64) && (rc = scale_positions(&sys->box, n, sys->x, sys->xs, s))) return rc;
+    }
+    int32_t longest = 0;
+    rc = build_neighbors(&sys->grid, n, sys->x, sys->cell_start, sys->row_cap, sys->idx, sys->count, sys->max_count,
+                         &longest, sys->ws, w, s);
+    if (rc == MD_ERR_CAPACITY) sys->row_cap_needed = longest;
+    if (rc) return rc;
+    ++sys->builds;
+    return MD_OK;
+}
+
+int forces(md_system_t *sys, const WsLayout &w, hipStream_t s)
+{
+    if (sys->potential == MD_POT_LJ)
+        return forces_lj(&sys->box, sys->n, sys->x, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->lj, sys->f,
+                         nullptr, sys->flags & (MD_PAIR_FP64 | MD_NO_COMPENSATE), sys->ws, w, s);
+    return forces_eam(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->fs, sys->rho,
+                      sys->fprime, static_cast<float *>(sys->f), nullptr, sys->flags & MD_NO_COMPENSATE, sys->ws, w,
+                      s);
+}
+
+// Optional timing of the force evaluations: one event pair per evaluation,
+// read back once the stream has passed it (the next flag wait or the end).
+struct ForceTimer {
+    bool on = false;
+    hipEvent_t ev[2][2] = {};
+    int pending = -1;   // slot with a recorded, unread pair
+    int next = 0;
+    bool init(bool want)
+    {
+        if (!want) return true;
+        for (auto &p : ev)
+            for (auto &e : p)
+                if (hipEventCreate(&e) != hipSuccess) return false;
+        on = true;
+        return true;
+    }
+    ~ForceTimer()
+    {
+        if (on)
+            for (auto &p : ev)
+                for (auto &e : p) (void)hipEventDestroy(e);
+    }
+    void start(hipStream_t s)
+    {
+        if (on) (void)hipEventRecord(ev[next][0], s);
+    }
+    void stop(hipStream_t s)
+    {
+        if (!on) return;
+        (void)hipEventRecord(ev[next][1], s);
+        pending = next;
+        next ^= 1;
+    }
+    void collect(md_system_t *sys, bool wait)
+    {
+        if (!on || pending < 0) return;
+        if (wait) (void)hipEventSynchronize(ev[pending][1]);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[pending][0], ev[pending][1]) == hipSuccess) {
+            sys->force_ms += ms;
+            ++sys->force_calls;
+        }
+        pending = -1;
+    }
+};
+
+}  // namespace
+
+int run(md_system_t *sys, int64_t steps, hipStream_t s)
+{
+    const WsLayout w = ws_layout(sys->grid.n_cells, sys->n);
+    const bool f64 = sys->flags & MD_PAIR_FP64;
+    const double hk = 0.5 * sys->dt * sys->accel;
+    uint32_t *xs = f64 ? nullptr : sys->xs;
+    int32_t *host_dev = nullptr;
+    if (sys->host_status) {
+        void *p = nullptr;
+        if (hipHostGetDevicePointer(&p, sys->host_status, 0) == hipSuccess) host_dev = static_cast<int32_t *>(p);
+        else (void)hipGetLastError();
+    }
+    int rc = MD_OK;
+    bool moved = false, bad = false;
+    ForceTimer timer;
+    if (!timer.init(sys->timing != 0)) return MD_ERR_HIP;
+    if (sys->phase == 0 && sys->need_build) {
+        if ((rc = rebuild(sys, w, s))) return rc;
+        sys->need_build = 0;
+        if ((rc = forces(sys, w, s))) return rc;
+    }
+    int64_t done = 0;
+    for (;;) {
+        if (sys->phase == 0) {
+            if (done >= steps) break;
+            const int32_t tag = int32_t(sys->step + 1);
+            if ((rc = kick_drift(&sys->box, sys->n, sys->x, sys->v, sys->f, f64, hk, sys->dt, sys->xref,
+                                 sys->half_skin_sq, sys->status, tag, xs, s)))
+                return rc;
+            sys->phase = 1;
+            if ((rc = wait_flag(sys, host_dev, tag, s, &moved, &bad))) return rc;
+            if (bad) return MD_ERR_NONFINITE;
+            sys->need_build |= moved ? 1 : 0;
+        }
+        // a step is in flight: positions drifted, forces stale
+        if (sys->need_build) {
+            if ((rc = rebuild(sys, w, s))) return rc;
+            sys->need_build = 0;
+        }
+        timer.start(s);
+        if ((rc = forces(sys, w, s))) return rc;
+        timer.stop(s);
+        ++sys->step;
+        ++done;
+        if (done < steps) {
+            // closing half kick of this step fused with the opening one of the next
+            const int32_t tag = int32_t(sys->step + 1);
+            if ((rc = kick_drift(&sys->box, sys->n, sys->x, sys->v, sys->f, f64, 2.0 * hk, sys->dt, sys->xref,
+                                 sys->half_skin_sq, sys->status, tag, xs, s)))
+                return rc;
+            if ((rc = wait_flag(sys, host_dev, tag, s, &moved, &bad))) return rc;
+            timer.collect(sys, false);   // the stream has passed the force evaluation
+            if (bad) return MD_ERR_NONFINITE;
+            sys->need_build |= moved ? 1 : 0;
+        } else {
+            if ((rc = integrate(MD_KICK, &sys->box, sys->n, sys->x, sys->v, sys->f, sys->dt, sys->accel, 1.0, nullptr,
+                                0.0, nullptr, 0, nullptr, nullptr, sys->flags & MD_PAIR_FP64, sys->ws, w, s)))
+                return rc;
+            sys->phase = 0;
+        }
+    }
+    timer.collect(sys, true);
+    return MD_OK;
+}
+
+}  // namespace md

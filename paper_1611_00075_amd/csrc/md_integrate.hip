@@ -85,6 +85,35 @@ __global__ __launch_bounds__(kBlock) void k_kick(int64_t n, double *__restrict__
     }
 }
 
+// v += kick * f; x += dt v; rebuild check; scaled coordinates.  kick is
+// dt/2 * accel for a half step, dt * accel when the closing half kick of the
+// previous step is fused in (same forces).
+int kick_drift(const md_box_t *box, int64_t n, double *x, double *v, const void *f, bool f64, double kick, double dt,
+               const double *xref, double half_skin_sq, int32_t *status, int32_t tag, uint32_t *xs, hipStream_t s)
+{
+    const uint32_t gb = uint32_t((n + kBlock - 1) / kBlock);
+    if (n <= 0) return MD_OK;
+    DriftArgs a;
+    a.hk = kick;
+    a.dt = dt;
+    for (int c = 0; c < 3; ++c) {
+        a.L[c] = box->L[c];
+        a.hL[c] = 0.5 * box->L[c];
+        a.k[c] = 4294967296.0 / box->L[c];
+    }
+    a.half_skin_sq = half_skin_sq;
+    a.tag = tag;
+    uint4 *q = reinterpret_cast<uint4 *>(xs);
+    if (f64)
+        hipLaunchKernelGGL(k_kick_drift<double>, dim3(gb), dim3(kBlock), 0, s, n, x, v, static_cast<const double *>(f),
+                           xref, status, q, a);
+    else
+        hipLaunchKernelGGL(k_kick_drift<float>, dim3(gb), dim3(kBlock), 0, s, n, x, v, static_cast<const float *>(f),
+                           xref, status, q, a);
+    MD_HIP_TRY(hipGetLastError());
+    return MD_OK;
+}
+
 int integrate(int32_t phase, const md_box_t *box, int64_t n, double *x, double *v, const void *f, double dt,
               double accel, double mass, const double *xref, double half_skin_sq, int32_t *status, int32_t tag,
               uint32_t *xs, double *ke, int32_t flags, void *ws, const WsLayout &w, hipStream_t s)
@@ -92,28 +121,8 @@ int integrate(int32_t phase, const md_box_t *box, int64_t n, double *x, double *
     const bool f64 = flags & MD_PAIR_FP64;
     const double hk = 0.5 * dt * accel;
     const uint32_t gb = uint32_t((n + kBlock - 1) / kBlock);
-    if (phase == MD_KICK_DRIFT) {
-        if (n <= 0) return MD_OK;
-        DriftArgs a;
-        a.hk = hk;
-        a.dt = dt;
-        for (int c = 0; c < 3; ++c) {
-            a.L[c] = box->L[c];
-            a.hL[c] = 0.5 * box->L[c];
-            a.k[c] = 4294967296.0 / box->L[c];
-        }
-        a.half_skin_sq = half_skin_sq;
-        a.tag = tag;
-        uint4 *q = reinterpret_cast<uint4 *>(xs);
-        if (f64)
-            hipLaunchKernelGGL(k_kick_drift<double>, dim3(gb), dim3(kBlock), 0, s, n, x, v,
-                               static_cast<const double *>(f), xref, status, q, a);
-        else
-            hipLaunchKernelGGL(k_kick_drift<float>, dim3(gb), dim3(kBlock), 0, s, n, x, v,
-                               static_cast<const float *>(f), xref, status, q, a);
-        MD_HIP_TRY(hipGetLastError());
-        return MD_OK;
-    }
+    if (phase == MD_KICK_DRIFT)
+        return kick_drift(box, n, x, v, f, f64, hk, dt, xref, half_skin_sq, status, tag, xs, s);
     if (phase != MD_KICK) return MD_ERR_ARG;
     double *part = ws_ptr<double>(ws, w.red1);
     if (int64_t(gb) > w.red_blocks) return MD_ERR_WORKSPACE;

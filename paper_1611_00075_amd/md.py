@@ -41,6 +41,25 @@ class FS(C.Structure):
                 ("c0", C.c_double), ("c1", C.c_double), ("c2", C.c_double)]
 
 
+class System(C.Structure):
+    """md_system_t of include/md.h."""
+    _fields_ = [("box", Box), ("grid", Grid), ("lj", LJ), ("fs", FS),
+                ("dt", C.c_double), ("accel", C.c_double), ("half_skin_sq", C.c_double),
+                ("n", C.c_int64), ("step", C.c_int64), ("builds", C.c_int64),
+                ("x", C.c_void_p), ("v", C.c_void_p), ("xref", C.c_void_p), ("scratch", C.c_void_p),
+                ("ids", C.c_void_p), ("ids_scratch", C.c_void_p), ("xs", C.c_void_p), ("f", C.c_void_p),
+                ("rho", C.c_void_p), ("fprime", C.c_void_p), ("cell", C.c_void_p), ("perm", C.c_void_p),
+                ("cell_start", C.c_void_p), ("idx", C.c_void_p), ("count", C.c_void_p),
+                ("max_count", C.c_void_p), ("status", C.c_void_p), ("host_status", C.c_void_p),
+                ("ws", C.c_void_p), ("ws_bytes", C.c_size_t), ("row_cap", C.c_int32),
+                ("row_cap_needed", C.c_int32), ("potential", C.c_int32), ("flags", C.c_int32),
+                ("need_build", C.c_int32), ("phase", C.c_int32), ("timing", C.c_int32), ("pad_", C.c_int32),
+                ("force_ms", C.c_double), ("force_calls", C.c_int64)]
+
+
+MD_POT_LJ, MD_POT_EAM = 0, 1
+
+
 class MDError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -77,6 +96,7 @@ def lib():
         L.md_integrate.argtypes = [C.c_int32, C.POINTER(Box), C.c_int64, _vp, _vp, _vp, C.c_double,
                                    C.c_double, C.c_double, _vp, C.c_double, _vp, C.c_int32, _vp, _vp,
                                    C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_run.argtypes = [C.POINTER(System), C.c_int64, _vp]
         _lib = L
     return _lib
 
@@ -234,3 +254,10 @@ def md_integrate(phase: int, L, n: int, x, v, f, dt: float, accel: float, mass: 
                               float(half_skin_sq), _ptr(status, torch.int32, 2, "status"), int(tag),
                               _ptr(xs, torch.int32, 4 * n, "xs"), _ptr(ke, torch.float64, 1, "ke"), int(flags),
                               _ptr(ws, name="ws"), ws.numel(), _stream(stream)), "md_integrate")
+
+
+def md_run(sys: System, steps: int, stream=None) -> int:
+    """Returns MD_OK or MD_ERR_CAPACITY (sys.row_cap_needed set); raises on
+    other errors."""
+    rc = lib().md_run(C.byref(sys), int(steps), _stream(stream))
+    return _check(rc, "md_run", allow=(MD_ERR_CAPACITY,))

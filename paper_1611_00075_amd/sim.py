@@ -81,6 +81,10 @@ class Simulation:
         self.builds = 0
         self.step_count = 0
         self._status_host = torch.zeros(2, dtype=torch.int32).pin_memory()
+        self._flag_host = torch.zeros(4, dtype=torch.int32).pin_memory()   # md_run's polled word
+        self._sys = M.System()
+        self._sys.need_build = 0
+        self._sys.phase = 0
         # optional per-phase timing: a list that step() appends
         # (phase, start_event, end_event) to, events recorded on the stream
         self.events = None
@@ -169,6 +173,48 @@ class Simulation:
         return rebuilt
 
     # ------------------------------------------------------------------
+    def _system(self) -> "M.System":
+        """md_system_t view of the current buffers (pointers refreshed)."""
+        S = self._sys
+        S.box = M.box(self.L)
+        S.grid = self.grid
+        S.lj = M.LJ(*self.lj)
+        if self.fs is not None:
+            S.fs = M.FS(self.fs["A"], self.fs["d"], self.fs["c"], self.fs["c0"], self.fs["c1"], self.fs["c2"])
+        S.dt, S.accel, S.half_skin_sq = self.dt, self.accel, self.half_skin_sq
+        S.n = self.n
+        S.step, S.builds = self.step_count, self.builds
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        S.x, S.v, S.xref, S.scratch = ptr(self.x), ptr(self.v), ptr(self.xref), ptr(self._x2)
+        S.ids, S.ids_scratch = ptr(self.ids), ptr(self._ids2)
+        S.xs, S.f, S.rho, S.fprime = ptr(self.xs), ptr(self.f), ptr(self.rho), ptr(self.fprime)
+        S.cell, S.perm, S.cell_start = ptr(self.cell), ptr(self.perm), ptr(self.cell_start)
+        S.idx, S.count, S.max_count = ptr(self.idx), ptr(self.count), ptr(self.max_count)
+        S.status, S.host_status = ptr(self.status), ptr(self._flag_host)
+        S.ws, S.ws_bytes = ptr(self.ws), self.ws.numel()
+        S.row_cap = self.row_cap
+        S.potential = M.MD_POT_LJ if self.potential == "lj" else M.MD_POT_EAM
+        S.flags = self.flags
+        return S
+
+    def run(self, steps: int, timing: bool = False):
+        """`steps` velocity-Verlet steps in the native driver (md_run).  With
+        timing, returns (summed force-kernel ms, force evaluations)."""
+        S = self._system()
+        S.timing = 1 if timing else 0
+        S.force_ms, S.force_calls = 0.0, 0
+        target = S.step + int(steps)
+        while S.step < target:
+            rc = M.md_run(S, target - S.step)
+            if rc == M.MD_ERR_CAPACITY:
+                self.row_cap = (int(S.row_cap_needed * self.list_slack) + 4 + 7) // 8 * 8
+                self.idx = torch.empty(max(M.ell_size(self.n, self.row_cap), 1), dtype=torch.int32,
+                                       device=self.dev)
+                S.idx, S.row_cap = self.idx.data_ptr(), self.row_cap
+                S.need_build = 1
+        self.step_count, self.builds = S.step, S.builds
+        return S.force_ms, S.force_calls
+
     def energies(self):
         """(potential, kinetic) of the current state, FP64; potential is
         E_shift for LJ and E_total for EAM (forces are recomputed)."""

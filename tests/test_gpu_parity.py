@@ -336,3 +336,80 @@ def test_vv_fp32_energy_conservation(M, orc):
     assert np.abs(np.array(e) - eo[::10]).max() / s.n < 1e-4
     # FP32 forces cancel only to rounding: total momentum stays small
     assert np.abs(sim.velocities().sum(0)).max() < 1e-3
+
+
+def test_md_run_matches_per_call_path(M, orc):
+    """The native driver (fused kicks) and the per-call API take the same
+    trajectory up to rounding, with the same list rebuilds."""
+    from paper_1611_00075_amd.sim import Simulation
+    s = inputs.lj_fcc(ncell=8)
+    a = Simulation(s.L, s.x, s.v, skin=0.3, dt=0.005, pair_fp64=True)
+    b = Simulation(s.L, s.x, s.v, skin=0.3, dt=0.005, pair_fp64=True)
+    for _ in range(60):
+        a.step()
+    b.run(25)
+    b.run(35)
+    assert a.builds == b.builds and b.step_count == 60
+    d = a.positions() - b.positions()
+    d -= s.L * np.round(d / s.L)
+    assert np.abs(d).max() < 1e-10
+    assert np.abs(a.velocities() - b.velocities()).max() < 1e-9
+
+
+def test_md_run_fp64_trajectory_within_oracle_envelope(M, orc):
+    from paper_1611_00075_amd.sim import Simulation
+    s = inputs.lj_fcc(ncell=10)
+    steps = 100
+    a = orc.md_run(s.x.copy(), s.v.copy(), s.L, steps, r_list=2.8, skin=0.3, dt=0.005)
+    b = orc.md_run(s.x.copy(), s.v.copy(), s.L, steps, r_list=2.8, skin=0.3, dt=0.005, reverse_order=True)
+    sim = Simulation(s.L, s.x, s.v, skin=0.3, dt=0.005, pair_fp64=True)
+    sim.run(steps)
+
+    def dev(p, q):
+        d = p - q
+        d -= s.L * np.round(d / s.L)
+        return np.abs(d).max()
+
+    env = max(dev(a["x"], b["x"]), 1e-13)
+    assert dev(sim.positions(), a["x"]) <= 10 * env, (dev(sim.positions(), a["x"]), env)
+    assert sim.builds == a["builds"]
+
+
+def test_md_run_capacity_protocol_resumes(M):
+    """A row capacity far too small: md_run stops with MD_ERR_CAPACITY in the
+    middle of a step, the caller grows the list and the run resumes to the
+    same state as an unconstrained run."""
+    from paper_1611_00075_amd.sim import Simulation
+    s = inputs.jitter(inputs.lj_fcc(ncell=8), 0.02, seed=5)
+    ref = Simulation(s.L, s.x, s.v, skin=0.3, dt=0.005, pair_fp64=True)
+    ref.run(40)
+    sim = Simulation(s.L, s.x, s.v, skin=0.3, dt=0.005, pair_fp64=True)
+    sim.row_cap = 8                      # force the protocol at the next rebuild
+    sim.idx = torch.empty(M.ell_size(sim.n, 8), dtype=torch.int32, device="cuda")
+    sim._sys.need_build = 1
+    sim.run(40)
+    assert sim.row_cap >= sim.longest or sim.row_cap > 8
+    d = sim.positions() - ref.positions()
+    d -= s.L * np.round(d / s.L)
+    assert np.abs(d).max() < 1e-10
+
+
+def test_md_run_eam_energy_conservation(M, orc):
+    """EAM (FP32 pair path) through the driver: the energy trace follows the
+    FP64 oracle's to FP32 accuracy."""
+    from paper_1611_00075_amd.sim import Simulation
+    s = inputs.eam_cu(ncell=6, T=600.0)
+    kw = dict(potential="eam", fs=inputs.FS_CU, skin=1.0, dt=1.0, mass=inputs.CU_MASS_AMU,
+              force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
+    sim = Simulation(s.L, s.x, s.v, **kw)
+    e = []
+    for k in range(5):
+        ep, ek = sim.energies()
+        e.append(ep + ek * inputs.AMU_A2_FS2_IN_EV)
+        sim.run(20)
+    ep, ek = sim.energies()
+    e.append(ep + ek * inputs.AMU_A2_FS2_IN_EV)
+    a = orc.md_run(s.x.copy(), s.v.copy(), s.L, 100, potential="eam", fs=inputs.FS_CU, r_list=5.4, skin=1.0,
+                   dt=1.0, mass=inputs.CU_MASS_AMU, force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
+    eo = a["epot"] + a["ekin"] * inputs.AMU_A2_FS2_IN_EV
+    assert np.abs(np.array(e) - eo[::20]).max() / s.n < 2e-5
