@@ -32,6 +32,21 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def recorded_traffic(key):
+    """HBM bytes per launch from the committed rocprofv3 counter runs
+    (profiles/traffic.json), or None when the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes"]
+
+
 def _phase_ms(sim):
     out = {}
     for name, a, b in sim.events:
@@ -126,7 +141,7 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "k_lj32 (md_forces_lj)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("k_lj32_lj_voids_1.23M"),
             "bytes_per_launch": byt, "launch_ms": f_ms,
         },
         "phases_ms_per_call_api": {k: v[0] for k, v in r["phases"].items()},

@@ -49,7 +49,21 @@ __global__ __launch_bounds__(kBlock) void k_bin_assign(int64_t n, double *x, Gri
     const int64_t lin = c[0] + int64_t(g.nc[0]) * (c[1] + int64_t(g.nc[1]) * c[2]);
     const int32_t r = lin2rank[lin];
     cell[i] = r;
-    slot[i] = atomicAdd(&cnt[r], 1);
+    // one atomic per distinct cell of the wave (atoms arrive nearly sorted):
+    // the first remaining lane claims a run of slots for all lanes of its
+    // cell, which take consecutive slots in lane order
+    uint64_t todo = __ballot(true);
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const int32_t rc = __builtin_amdgcn_readlane(r, leader);
+        const uint64_t same = __ballot(r == rc) & todo;
+        int32_t base = 0;
+        if ((threadIdx.x % kWave) == leader) base = atomicAdd(&cnt[rc], __popcll(same));
+        base = __builtin_amdgcn_readlane(base, leader);
+        if (r == rc && ((todo >> (threadIdx.x % kWave)) & 1u))
+            slot[i] = base + __builtin_amdgcn_mbcnt_hi(uint32_t(same >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(same), 0u));
+        todo &= ~same;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_bin_scatter(int64_t n, const int32_t *cell, const int32_t *slot,
@@ -193,13 +207,21 @@ __device__ __forceinline__ int stencil_axis(int32_t c, int32_t nc, int32_t reach
     return m;
 }
 
-__device__ __forceinline__ double minimg(double d, double L, double hL)
+// Wave-uniform copies of values the compiler cannot prove uniform.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double lane_f64(double v, int l)
 {
-    if (d > hL)
-        d -= L;
-    else if (d < -hL)
-        d += L;
-    return d;
+    const int64_t b = __double_as_longlong(v);
+    const int32_t lo = __builtin_amdgcn_readlane(int32_t(b), l), hi = __builtin_amdgcn_readlane(int32_t(b >> 32), l);
+    return __longlong_as_double((int64_t(hi) << 32) | int64_t(uint32_t(lo)));
+}
+
+// The definition's minimum image without branches: subtracting 0, L or -L
+// gives the same bits as leaving d alone, d - L or d + L.
+__device__ __forceinline__ double minimg_sel(double d, double L, double hL)
+{
+    const double t = d > hL ? L : (d < -hL ? -L : 0.0);
+    return d - t;
 }
 
 __device__ __forceinline__ void wave_sync()
@@ -240,16 +262,16 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(int64_t n, const double *x
                                                       int32_t *max_count)
 {
     __shared__ NbWaveLds lds_all[kNbWaves];
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave, wave = uni(threadIdx.x / kWave);
     NbWaveLds &L = lds_all[wave];
     const int64_t rank = int64_t(xcd_block(blockIdx.x, gridDim.x)) * kNbWaves + wave;
     if (rank >= n_cells) return;
-    const int32_t h0 = cell_start[rank], h1 = cell_start[rank + 1];
+    const int32_t h0 = uni(cell_start[rank]), h1 = uni(cell_start[rank + 1]);
     if (h0 == h1) return;
 
     // stencil cells: lane t takes cells t and t + 64 (x-fastest order), reads
     // their ranges, and a shuffle scan forms the range prefix
-    const int32_t pk = rank_xyz[rank];        // packed cell coordinates
+    const int32_t pk = uni(rank_xyz[rank]);   // packed cell coordinates
     const int32_t c3[3] = {pk & 1023, (pk >> 10) & 1023, pk >> 20};
     bool interior = true;
     for (int a = 0; a < 3; ++a)
@@ -282,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(int64_t n, const double *x
             if (lane >= o) v += u;
         }
         if (t < m) L.rbase[t + 1] = carry + v;
-        carry += __shfl(v, kWave - 1, kWave);
+        carry += __builtin_amdgcn_readlane(v, kWave - 1);
     }
     if (lane == 0) L.rbase[0] = 0;
     wave_sync();
@@ -314,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(int64_t n, const double *x
             wave_sync();
             for (int32_t h = 0; h < hn; ++h) {
                 const int32_t i = hb + h;
-                const double xi = __shfl(xl, h, kWave), yi = __shfl(yl, h, kWave), zi = __shfl(zl, h, kWave);
+                const double xi = lane_f64(xl, h), yi = lane_f64(yl, h), zi = lane_f64(zl, h);
                 int32_t r = __builtin_amdgcn_readlane(run_l, h);
                 int32_t *row = idx + (int64_t(i >> 3) * row_cap * 8 + (i & 7) * 8);
                 for (int32_t c0 = 0; c0 < tn; c0 += kWave) {
@@ -323,9 +345,9 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(int64_t n, const double *x
                     if (q < tn) {
                         double dx = L.sx[q] - xi, dy = L.sy[q] - yi, dz = L.sz[q] - zi;
                         if (!interior) {
-                            dx = minimg(dx, g.L[0], g.hL[0]);
-                            dy = minimg(dy, g.L[1], g.hL[1]);
-                            dz = minimg(dz, g.L[2], g.hL[2]);
+                            dx = minimg_sel(dx, g.L[0], g.hL[0]);
+                            dy = minimg_sel(dy, g.L[1], g.hL[1]);
+                            dz = minimg_sel(dz, g.L[2], g.hL[2]);
                         }
                         const double r2 = (dx * dx + dy * dy) + dz * dz;
                         hit = (L.sj[q] != i) && (r2 < rl2);
