@@ -53,6 +53,7 @@ const char *md_error_string(int status);
 #define MD_ENERGY        0x1  /* forces: also write energy and virial to ev */
 #define MD_PAIR_FP64     0x2  /* forces: FP64 pair arithmetic, FP64 forces */
 #define MD_NO_COMPENSATE 0x4  /* forces: plain FP32 accumulation (timing aid) */
+#define MD_MLP_REUSE     0x8  /* md_forces_mlp: dEdG already holds dE_i/dG_i */
 
 /* ---- geometry ---- */
 
@@ -195,12 +196,118 @@ typedef struct md_fs {
  * FP32 pair arithmetic from the scaled coordinates xs (written by
  * md_scale_positions; xs[4i+3] is overwritten with F'_i), compensated FP32
  * sums.  Outputs: rho[n], fprime[n] (float), f float[3n] (overwritten); with
- * MD_ENERGY, ev[8] = E_total, E_embed, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz. */
+ * MD_ENERGY, ev[8] = E_total, E_embed, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz,
+ * and, if e_atom is not NULL, the site energies
+ * e_atom[i] = F(rho_i) + 1/2 sum_j V(r_ij) (float; needs MD_ENERGY). */
 int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs,
                   int32_t row_cap, const int32_t *idx, const int32_t *count,
                   const md_fs_t *fs, float *rho, float *fprime, float *f,
-                  double *ev, int32_t flags, void *ws, size_t ws_bytes,
-                  void *stream);
+                  float *e_atom, double *ev, int32_t flags, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* ---- steps a8/a9: learned descriptor-MLP potential ----
+ *
+ * A learned stand-in for the embedded-atom energy of Eqs. (1)-(2): like
+ * F(rho_i) + 1/2 sum_j V(r_ij), the energy of atom i is a function of the
+ * distances to its neighbours only.
+ *   pair basis  g_k(r) = exp(-(r - mu_k)^2 / (2 w^2)) fc(r) for r < rc,
+ *               fc(r) = (cos(pi r / rc) + 1) / 2, mu_k = mu0 + k dmu, k < 16;
+ *   descriptor  G_ik = sum_{j in N(i), r_ij < rc} g_k(r_ij);
+ *   network     x = (G_i - mean) * inv_std, h1 = silu(W1 x + b1),
+ *               h2 = silu(W2 h1 + b2), E_i = w3 . h2 + b3 (16 -> 64 -> 64
+ *               -> 1, silu(a) = a / (1 + exp(-a)));
+ *   forces      F_i = -dE/dx_i, E = sum_i E_i.
+ * Parameters: MD_MLP_NPARAM bfloat16 values (uint16 bit patterns), row-major
+ * matrices with the output index first: W1[64][16], b1[64], W2[64][64],
+ * b2[64], w3[64], b3.  The matrix products run on the BF16 matrix cores with
+ * FP32 accumulation: every vector entering a product (x, h1, and the
+ * back-propagated vectors dE/da2, dE/da1) is rounded to bfloat16 (round to
+ * nearest even); pre-activations, SiLU and its derivative, biases, the last
+ * layer and all sums over neighbours are FP32. */
+#define MD_MLP_IN     16
+#define MD_MLP_HID    64
+#define MD_MLP_NPARAM 5313
+
+typedef struct md_mlp {
+    double rc;                  /* descriptor cutoff */
+    double mu0, dmu;            /* Gaussian centres mu_k = mu0 + k dmu */
+    double width;               /* Gaussian width w */
+    float mean[MD_MLP_IN];      /* input normalisation */
+    float inv_std[MD_MLP_IN];
+} md_mlp_t;
+
+/* Raw descriptors G[n][16] (float, row i contiguous) from a full list at
+ * any list cutoff >= rc (the output of md_build_neighbors) and the scaled
+ * coordinates xs of md_scale_positions.  FP32; the 16 Gaussians of a pair
+ * are formed from three exponentials by their ratio recurrence (exact up to
+ * rounding for r > 1 A with the default centres and width). */
+int md_mlp_descriptors(const md_box_t *box, int64_t n, const uint32_t *xs,
+                       int32_t row_cap, const int32_t *idx,
+                       const int32_t *count, const md_mlp_t *mlp, float *G,
+                       void *stream);
+
+/* The network alone on given raw descriptors G[n][16]: per-atom energies
+ * e_atom[n] and, if dEdG is not NULL, dE_i/dG_i [n][16] (float). */
+int md_mlp_eval(int64_t n, const float *G, const md_mlp_t *mlp,
+                const uint16_t *w, float *e_atom, float *dEdG, void *stream);
+
+/* Forces of the learned potential in two passes over the full list (the
+ * same two-pass shape as md_forces_eam):
+ *   pass 1: G_i, the network and its backward pass to dE_i/dG_i, stored in
+ *           dEdG[n][16] (caller-owned float scratch);
+ *   pass 2: F_i = -sum_{j, r_ij < rc} s_ij (r_i - r_j) / r_ij with
+ *           s_ij = sum_k (dE_i/dG_ik + dE_j/dG_jk) g_k'(r_ij).
+ * f is float[3n], overwritten; compensated FP32 sums.  e_atom (may be NULL)
+ * receives E_i.  With MD_ENERGY, ev[8] = E, E, W_xx, W_yy, W_zz, W_xy, W_xz,
+ * W_yz (W_ab = -1/2 sum_i sum_j s_ij R_a R_b / r_ij), FP64 in fixed order.
+ * With MD_MLP_REUSE, pass 1 is skipped and dEdG is taken as given (the
+ * stored result of an earlier call on the same positions, or the caller's
+ * own); w and e_atom are then unused and E in ev is 0.
+ * ws as for md_forces_lj. */
+int md_forces_mlp(const md_box_t *box, int64_t n, const uint32_t *xs,
+                  int32_t row_cap, const int32_t *idx, const int32_t *count,
+                  const md_mlp_t *mlp, const uint16_t *w, float *dEdG,
+                  float *e_atom, float *f, double *ev, int32_t flags,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* Host only.  Bytes of training workspace for batches of up to `batch`
+ * atoms (md_mlp_moments, md_mlp_grad, md_mlp_train_step). */
+size_t md_mlp_workspace_bytes(int64_t batch);
+
+/* Per-component mean and standard deviation (population) of G[n][16]:
+ * moments[0..15] = mean, moments[16..31] = std (device double[32]), FP64
+ * sums in a fixed order. */
+int md_mlp_moments(int64_t n, const float *G, double *moments, void *tws,
+                   size_t tws_bytes, void *stream);
+
+/* Per-atom energy loss of a batch, L = (1/B) sum_b (E(G[sel[b]]) -
+ * target[sel[b]])^2 (sel may be NULL: rows 0..B-1), and its gradient with
+ * respect to the parameters (float[MD_MLP_NPARAM], the layout of w) by back
+ * propagation: BF16 matrix-core products for dL/dW1, dL/dW2 and the
+ * backward pass, FP32 sums for the biases and w3, per-block partials summed
+ * in FP64 in a fixed order.  *loss (device double, may be NULL) = L. */
+int md_mlp_grad(int64_t batch, const int32_t *sel, const float *G,
+                const float *target, const md_mlp_t *mlp, const uint16_t *w,
+                float *grad, double *loss, void *tws, size_t tws_bytes,
+                void *stream);
+
+/* Adam (Kingma & Ba) on FP32 master weights. */
+typedef struct md_adam {
+    double lr, beta1, beta2, eps;
+    int64_t step;               /* 1 for the first update */
+} md_adam_t;
+
+/* One optimiser step: the gradient of md_mlp_grad, then per parameter
+ * m1 = b1 m1 + (1-b1) g, m2 = b2 m2 + (1-b2) g^2,
+ * master -= lr (m1 / (1-b1^step)) / (sqrt(m2 / (1-b2^step)) + eps)   (FP32)
+ * and w = bfloat16(master) (round to nearest even).  master, m1, m2 are
+ * float[MD_MLP_NPARAM]; w is both the network used for the gradient and the
+ * refreshed copy.  *loss (may be NULL) = the batch loss before the step. */
+int md_mlp_train_step(int64_t batch, const int32_t *sel, const float *G,
+                      const float *target, const md_mlp_t *mlp,
+                      const md_adam_t *adam, float *master, float *m1,
+                      float *m2, uint16_t *w, double *loss, void *tws,
+                      size_t tws_bytes, void *stream);
 
 /* ---- step a7: velocity Verlet ---- */
 
@@ -228,6 +335,7 @@ int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x,
 
 #define MD_POT_LJ  0
 #define MD_POT_EAM 1
+#define MD_POT_MLP 2
 
 /* One system for md_run.  The caller fills every field (device buffers are
  * caller-owned; sizes as for the calls above) and keeps the struct between
@@ -257,7 +365,7 @@ typedef struct md_system {
     size_t ws_bytes;
     int32_t row_cap;
     int32_t row_cap_needed;     /* out: set with MD_ERR_CAPACITY */
-    int32_t potential;          /* MD_POT_LJ or MD_POT_EAM */
+    int32_t potential;          /* MD_POT_LJ, MD_POT_EAM or MD_POT_MLP */
     int32_t flags;              /* MD_PAIR_FP64 (LJ only), MD_NO_COMPENSATE */
     int32_t need_build;         /* 1: build lists (and forces) before stepping */
     int32_t phase;              /* 0: at a step boundary; 1: a step is in flight */
@@ -265,12 +373,15 @@ typedef struct md_system {
     int32_t pad_;
     double force_ms;            /* out (timing): summed force-kernel time */
     int64_t force_calls;        /* out (timing): force evaluations timed */
+    md_mlp_t mlp;               /* MD_POT_MLP */
+    const uint16_t *mlp_w;      /* MD_POT_MLP: MD_MLP_NPARAM bfloat16 parameters */
+    float *dEdG;                /* MD_POT_MLP: [16n] scratch */
 } md_system_t;
 
 /* Runs `steps` velocity-Verlet steps (Sec. 3.3) of the path: kick + drift
  * with the rebuild check, md_bin_cells + md_permute + md_scale_positions +
  * md_build_neighbors whenever some atom moved more than skin/2 since the
- * last build, forces (md_forces_lj or md_forces_eam), kick.  Between two
+ * last build, forces (md_forces_lj, md_forces_eam or md_forces_mlp), kick.  Between two
  * steps the closing half kick and the next opening half kick are applied as
  * one kick with the same forces.  On entry with need_build set (a new
  * system) the lists and forces are built first; otherwise f must hold the

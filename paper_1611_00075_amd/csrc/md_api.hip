@@ -53,6 +53,17 @@ int ws_check_n(int64_t n, void *ws, size_t bytes, WsLayout &w)
     return MD_OK;
 }
 
+// descriptor geometry: positive width and spacing, 0 < rc, finite
+// normalisation
+bool mlp_ok(const md_mlp_t *m)
+{
+    if (!m || !(m->rc > 0.0) || !(m->width > 0.0) || !(m->dmu > 0.0) || !std::isfinite(m->mu0)) return false;
+    if (!std::isfinite(m->rc) || !std::isfinite(m->width) || !std::isfinite(m->dmu)) return false;
+    for (int k = 0; k < MD_MLP_IN; ++k)
+        if (!std::isfinite(m->mean[k]) || !std::isfinite(m->inv_std[k])) return false;
+    return true;
+}
+
 uint64_t spread3(uint64_t v)
 {
     uint64_t r = 0;
@@ -220,8 +231,8 @@ int md_forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t
 }
 
 int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t row_cap, const int32_t *idx,
-                  const int32_t *count, const md_fs_t *fs, float *rho, float *fprime, float *f, double *ev,
-                  int32_t flags, void *ws, size_t ws_bytes, void *stream)
+                  const int32_t *count, const md_fs_t *fs, float *rho, float *fprime, float *f, float *e_atom,
+                  double *ev, int32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
     if (!fs || !(fs->d > 0.0) || !(fs->c > 0.0) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8)
@@ -229,9 +240,79 @@ int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t row_cap,
     if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE)) return MD_ERR_ARG;
     if (n > 0 && (!xs || !idx || !count || !rho || !fprime || !f)) return MD_ERR_ARG;
     if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
+    if (e_atom && !(flags & MD_ENERGY)) return MD_ERR_ARG;
     WsLayout w;
     if (int rc = ws_check_n(n, ws, ws_bytes, w)) return rc;
-    return forces_eam(box, n, xs, row_cap, idx, count, fs, rho, fprime, f, ev, flags, ws, w, as_stream(stream));
+    return forces_eam(box, n, xs, row_cap, idx, count, fs, rho, fprime, f, e_atom, ev, flags, ws, w,
+                      as_stream(stream));
+}
+
+int md_mlp_descriptors(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t row_cap, const int32_t *idx,
+                       const int32_t *count, const md_mlp_t *mlp, float *G, void *stream)
+{
+    if (!box_ok(box)) return MD_ERR_BOX;
+    if (!mlp_ok(mlp) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8) return MD_ERR_ARG;
+    if (n > 0 && (!xs || !idx || !count || !G)) return MD_ERR_ARG;
+    return mlp_descriptors(box, n, xs, row_cap, idx, count, mlp, G, as_stream(stream));
+}
+
+int md_mlp_eval(int64_t n, const float *G, const md_mlp_t *mlp, const uint16_t *w, float *e_atom, float *dEdG,
+                void *stream)
+{
+    if (!mlp_ok(mlp) || n < 0 || n > kMaxAtoms) return MD_ERR_ARG;
+    if (n > 0 && (!G || !w || !e_atom)) return MD_ERR_ARG;
+    return mlp_eval(n, G, mlp, w, e_atom, dEdG, as_stream(stream));
+}
+
+int md_forces_mlp(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t row_cap, const int32_t *idx,
+                  const int32_t *count, const md_mlp_t *mlp, const uint16_t *w, float *dEdG, float *e_atom, float *f,
+                  double *ev, int32_t flags, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!box_ok(box)) return MD_ERR_BOX;
+    if (!mlp_ok(mlp) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8) return MD_ERR_ARG;
+    if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE | MD_MLP_REUSE)) return MD_ERR_ARG;
+    if (n > 0 && (!xs || !idx || !count || !dEdG || !f)) return MD_ERR_ARG;
+    if (n > 0 && !(flags & MD_MLP_REUSE) && !w) return MD_ERR_ARG;
+    if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
+    WsLayout wl;
+    if (int rc = ws_check_n(n, ws, ws_bytes, wl)) return rc;
+    return forces_mlp(box, n, xs, row_cap, idx, count, mlp, w, dEdG, e_atom, f, ev, flags, ws, wl,
+                      as_stream(stream));
+}
+
+size_t md_mlp_workspace_bytes(int64_t batch)
+{
+    if (batch < 0 || batch > kMaxAtoms) return 0;
+    return mlp_workspace_bytes(batch);
+}
+
+int md_mlp_moments(int64_t n, const float *G, double *moments, void *tws, size_t tws_bytes, void *stream)
+{
+    if (n < 1 || n > kMaxAtoms || !G || !moments) return MD_ERR_ARG;
+    if (!tws || tws_bytes < mlp_workspace_bytes(0)) return MD_ERR_WORKSPACE;
+    return mlp_moments(n, G, moments, tws, as_stream(stream));
+}
+
+int md_mlp_grad(int64_t batch, const int32_t *sel, const float *G, const float *target, const md_mlp_t *mlp,
+                const uint16_t *w, float *grad, double *loss, void *tws, size_t tws_bytes, void *stream)
+{
+    if (!mlp_ok(mlp) || batch < 1 || batch > kMaxAtoms || !G || !target || !w || !grad) return MD_ERR_ARG;
+    if (!tws || tws_bytes < mlp_workspace_bytes(batch)) return MD_ERR_WORKSPACE;
+    return mlp_grad_update(batch, sel, G, target, mlp, w, grad, loss, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           tws, as_stream(stream));
+}
+
+int md_mlp_train_step(int64_t batch, const int32_t *sel, const float *G, const float *target, const md_mlp_t *mlp,
+                      const md_adam_t *adam, float *master, float *m1, float *m2, uint16_t *w, double *loss,
+                      void *tws, size_t tws_bytes, void *stream)
+{
+    if (!mlp_ok(mlp) || batch < 1 || batch > kMaxAtoms || !G || !target || !w) return MD_ERR_ARG;
+    if (!adam || !master || !m1 || !m2 || adam->step < 1 || !(adam->lr >= 0.0) || !(adam->eps > 0.0) ||
+        !(adam->beta1 >= 0.0 && adam->beta1 < 1.0) || !(adam->beta2 >= 0.0 && adam->beta2 < 1.0))
+        return MD_ERR_ARG;
+    if (!tws || tws_bytes < mlp_workspace_bytes(batch)) return MD_ERR_WORKSPACE;
+    return mlp_grad_update(batch, sel, G, target, mlp, w, nullptr, loss, adam, master, m1, m2, w, tws,
+                           as_stream(stream));
 }
 
 int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x, double *v, const void *f, double dt,
@@ -255,9 +336,11 @@ int md_run(md_system_t *sys, int64_t steps, void *stream)
 {
     if (!sys || steps < 0 || !box_ok(&sys->box) || !grid_ok(&sys->grid) || sys->n < 0 || sys->n > kMaxAtoms)
         return MD_ERR_ARG;
-    if (sys->potential != MD_POT_LJ && sys->potential != MD_POT_EAM) return MD_ERR_ARG;
+    if (sys->potential != MD_POT_LJ && sys->potential != MD_POT_EAM && sys->potential != MD_POT_MLP)
+        return MD_ERR_ARG;
     if (sys->flags & ~(MD_PAIR_FP64 | MD_NO_COMPENSATE)) return MD_ERR_ARG;
-    if (sys->potential == MD_POT_EAM && (sys->flags & MD_PAIR_FP64)) return MD_ERR_ARG;
+    if (sys->potential != MD_POT_LJ && (sys->flags & MD_PAIR_FP64)) return MD_ERR_ARG;
+    if (sys->potential == MD_POT_MLP && !mlp_ok(&sys->mlp)) return MD_ERR_ARG;
     if (sys->row_cap < 8 || sys->row_cap % 8 || (sys->phase != 0 && sys->phase != 1)) return MD_ERR_ARG;
     for (int a = 0; a < 3; ++a)
         if (sys->grid.L[a] != sys->box.L[a]) return MD_ERR_ARG;
@@ -269,6 +352,7 @@ int md_run(md_system_t *sys, int64_t steps, void *stream)
             return MD_ERR_ARG;
         if (!f64 && !sys->xs) return MD_ERR_ARG;
         if (sys->potential == MD_POT_EAM && (!sys->rho || !sys->fprime)) return MD_ERR_ARG;
+        if (sys->potential == MD_POT_MLP && (!sys->mlp_w || !sys->dEdG)) return MD_ERR_ARG;
     }
     WsLayout w;
     if (int rc = ws_check(&sys->grid, sys->n, sys->ws, sys->ws_bytes, w)) return rc;

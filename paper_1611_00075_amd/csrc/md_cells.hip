@@ -224,13 +224,6 @@ __device__ __forceinline__ double minimg_sel(double d, double L, double hL)
     return d - t;
 }
 
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 constexpr int kNbWaveTile = 128;       // candidates staged per wave at once
 constexpr int kNbWaves = kBlock / kWave;
 

@@ -29,6 +29,15 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G)
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// Orders the LDS accesses of one wavefront around this point (the lanes of a
+// wave exchange data through LDS without a block barrier).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int width)
 {
@@ -127,10 +136,22 @@ int build_neighbors(const md_grid_t *, int64_t, const double *, const int32_t *,
 int forces_lj(const md_box_t *, int64_t, const double *, const uint32_t *, int32_t, const int32_t *, const int32_t *,
               const md_lj_t *, void *, double *, int32_t, void *, const WsLayout &, hipStream_t);
 int forces_eam(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, const int32_t *, const md_fs_t *,
-               float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t);
+               float *, float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t);
 int integrate(int32_t, const md_box_t *, int64_t, double *, double *, const void *, double, double, double,
               const double *, double, int32_t *, int32_t, uint32_t *, double *, int32_t, void *, const WsLayout &,
               hipStream_t);
+int mlp_descriptors(const md_box_t *, int64_t, const uint32_t *, int32_t, const int32_t *, const int32_t *,
+                    const md_mlp_t *, float *, hipStream_t);
+int mlp_eval(int64_t, const float *, const md_mlp_t *, const uint16_t *, float *, float *, hipStream_t);
+int forces_mlp(const md_box_t *, int64_t, const uint32_t *, int32_t, const int32_t *, const int32_t *,
+               const md_mlp_t *, const uint16_t *, float *, float *, float *, double *, int32_t, void *,
+               const WsLayout &, hipStream_t);
+size_t mlp_workspace_bytes(int64_t batch);
+int mlp_moments(int64_t, const float *, double *, void *, hipStream_t);
+// gradient of the batch loss (grad, loss may be NULL); with adam, an Adam
+// step on master/m1/m2 and the refreshed bfloat16 copy w_out
+int mlp_grad_update(int64_t, const int32_t *, const float *, const float *, const md_mlp_t *, const uint16_t *,
+                    float *, double *, const md_adam_t *, float *, float *, float *, uint16_t *, void *, hipStream_t);
 int run(md_system_t *sys, int64_t steps, hipStream_t s);
 int kick_drift(const md_box_t *box, int64_t n, double *x, double *v, const void *f, bool f64, double kick, double dt,
                const double *xref, double half_skin_sq, int32_t *status, int32_t tag, uint32_t *xs, hipStream_t s);

@@ -20,88 +20,9 @@
 // s = L/2^32 (cutoffs and constants are pre-scaled on the host); the unit
 // vector of a pair does not depend on the unit.  Pair arithmetic is FP32;
 // per-lane sums are Kahan-compensated unless MD_NO_COMPENSATE.
-#include "md_common.h"
+#include "md_pair.h"
 
 namespace md {
-
-template <bool COMP>
-__device__ __forceinline__ void acc_add(float &s, float &c, float a, float b)
-{
-    // s += a * b, with the running error of the sum compensated
-    if (COMP) {
-        const float y = __builtin_fmaf(a, b, -c);
-        const float t = s + y;
-        c = (t - s) - y;
-        s = t;
-    } else {
-        s = __builtin_fmaf(a, b, s);
-    }
-}
-
-// Displacement r_i - r_j from scaled coordinates.  CUBIC: in units of
-// L/2^32 (no multiply); otherwise in physical units (ax = L_a / 2^32).
-template <bool CUBIC>
-__device__ __forceinline__ void disp(const uint4 &pi, const uint4 &pj, float ax, float ay, float az, float &dx,
-                                     float &dy, float &dz)
-{
-    dx = float(int32_t(pi.x - pj.x));
-    dy = float(int32_t(pi.y - pj.y));
-    dz = float(int32_t(pi.z - pj.z));
-    if (!CUBIC) {
-        dx *= ax;
-        dy *= ay;
-        dz *= az;
-    }
-}
-
-// Sliced-ELL row of atom i: entry e at row[(e / 8) * 64 + e % 8].
-__device__ __forceinline__ const int32_t *ell_row(const int32_t *idx, int64_t i, int32_t cap)
-{
-    return idx + (int64_t(i / kSlice) * cap * kSlice + (i % kSlice) * kSlice);
-}
-
-__device__ __forceinline__ int64_t ell_pos(int32_t e) { return int64_t(e / kSlice) * (kSlice * kSlice) + e % kSlice; }
-
-// Walk row entries [0, cnt) with stride U*TPA starting at `sub`;
-// body(pj, valid).  With lane = 8 * atom + sub the lanes of a wave read one
-// contiguous 256-byte run of the list per load, and each quarter-wave
-// gathers 8 consecutive neighbours of one atom.
-template <int TPA, int U, typename Body>
-__device__ __forceinline__ void walk_row(const uint4 *__restrict__ xs, const int32_t *__restrict__ row, int32_t cnt,
-                                         int sub, Body &&body)
-{
-    for (int32_t t = sub; t < cnt; t += U * TPA) {
-        int32_t j[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) j[u] = row[ell_pos(min(t + u * TPA, cnt - 1))];
-        uint4 pj[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) pj[u] = xs[j[u]];
-#pragma unroll
-        for (int u = 0; u < U; ++u) body(pj[u], t + u * TPA < cnt);
-    }
-}
-
-// The 8 lanes of one atom are consecutive: combine over them in FP64.
-__device__ __forceinline__ double combine(float s, float c)
-{
-    double g = double(s) - double(c);
-#pragma unroll
-    for (int o = 1; o < kSlice; o <<= 1) g += __shfl_xor(g, o, kWave);
-    return g;
-}
-
-// Atom and lane-in-atom of this thread: a wave holds one slice of kSlice
-// atoms, lane = kSlice * a + sub.
-struct SliceLane {
-    int64_t i;
-    int sub;
-};
-
-__device__ __forceinline__ SliceLane slice_lane(uint32_t blk)
-{
-    return {int64_t(blk) * (kBlock / kSlice) + threadIdx.x / kSlice, int(threadIdx.x % kSlice)};
-}
 
 // ---------------------------------------------------------------------------
 // Lennard-Jones, FP32 pair arithmetic
@@ -315,7 +236,8 @@ template <int TPA, int U, bool CUBIC, bool ENERGY, bool COMP>
 __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__restrict__ xs,
                                                       int32_t cap, const int32_t *__restrict__ idx,
                                                       const int32_t *__restrict__ count, FS32 p,
-                                                      float *__restrict__ f, double *__restrict__ part)
+                                                      const float *__restrict__ rho, float *__restrict__ f,
+                                                      float *__restrict__ e_atom, double *__restrict__ part)
 {
     static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -358,6 +280,17 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
         f[i] = float(gx);
         f[n + i] = float(gy);
         f[2 * n + i] = float(gz);
+    }
+    if (ENERGY && e_atom) {
+        // site energy F(rho_i) + 1/2 sum_j V(r_ij); F as in the first pass
+        double ei = e;
+#pragma unroll
+        for (int o = 1; o < kSlice; o <<= 1) ei += __shfl_xor(ei, o, kWave);
+        if (sub == 0 && i < n) {
+            const float r = rho[i];
+            const float F = r > 0.f ? -p.A * __builtin_amdgcn_sqrtf(r) : 0.f;
+            e_atom[i] = float(double(F) + 0.5 * ei);
+        }
     }
     if (ENERGY) {
         __shared__ double lds[8 * (kBlock / kWave)];
@@ -464,27 +397,27 @@ int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *x
 
 template <int TPA, bool CUBIC, bool E, bool C>
 static void launch_eam(uint32_t gb, hipStream_t s, int64_t n, uint4 *q, const List &l, const FS32 &p, float *rho,
-                       float *fprime, float *f, double *part1, double *part2)
+                       float *fprime, float *f, float *ea, double *part1, double *part2)
 {
     hipLaunchKernelGGL((k_eam_rho<TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx,
                        l.cnt, p, rho, fprime, part1);
     hipLaunchKernelGGL((k_eam_force<TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx,
-                       l.cnt, p, f, part2);
+                       l.cnt, p, rho, f, ea, part2);
 }
 
 template <int TPA, bool CUBIC>
 static void dispatch_eam(bool e, bool c, uint32_t gb, hipStream_t s, int64_t n, uint4 *q, const List &l,
-                         const FS32 &p, float *rho, float *fprime, float *f, double *p1, double *p2)
+                         const FS32 &p, float *rho, float *fprime, float *f, float *ea, double *p1, double *p2)
 {
-    if (e && c) launch_eam<TPA, CUBIC, true, true>(gb, s, n, q, l, p, rho, fprime, f, p1, p2);
-    else if (e) launch_eam<TPA, CUBIC, true, false>(gb, s, n, q, l, p, rho, fprime, f, p1, p2);
-    else if (c) launch_eam<TPA, CUBIC, false, true>(gb, s, n, q, l, p, rho, fprime, f, p1, p2);
-    else launch_eam<TPA, CUBIC, false, false>(gb, s, n, q, l, p, rho, fprime, f, p1, p2);
+    if (e && c) launch_eam<TPA, CUBIC, true, true>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
+    else if (e) launch_eam<TPA, CUBIC, true, false>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
+    else if (c) launch_eam<TPA, CUBIC, false, true>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
+    else launch_eam<TPA, CUBIC, false, false>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
 }
 
 int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
-               const md_fs_t *fs, float *rho, float *fprime, float *f, double *ev, int32_t flags, void *ws,
-               const WsLayout &w, hipStream_t s)
+               const md_fs_t *fs, float *rho, float *fprime, float *f, float *e_atom, double *ev, int32_t flags,
+               void *ws, const WsLayout &w, hipStream_t s)
 {
     const List l{cap, idx, cnt};
     const bool energy = flags & MD_ENERGY;
@@ -511,8 +444,8 @@ int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const 
     p.A = float(fs->A);
     uint4 *q = reinterpret_cast<uint4 *>(xs);
     if (n > 0) {
-        if (cubic) dispatch_eam<kTPA, true>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, part1, part2);
-        else dispatch_eam<kTPA, false>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, part1, part2);
+        if (cubic) dispatch_eam<kTPA, true>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, e_atom, part1, part2);
+        else dispatch_eam<kTPA, false>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, e_atom, part1, part2);
         MD_HIP_TRY(hipGetLastError());
     }
     if (energy) return launch_reduce_partials(part1, gb, part2, gb, ev, kReduceEAM, 0.0, 0.0, s);

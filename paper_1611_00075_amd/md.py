@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 MD_OK, MD_ERR_ARG, MD_ERR_BOX, MD_ERR_CAPACITY = 0, -1, -2, -3
 MD_ERR_NONFINITE, MD_ERR_HIP, MD_ERR_WORKSPACE = -4, -5, -6
-MD_ENERGY, MD_PAIR_FP64, MD_NO_COMPENSATE = 0x1, 0x2, 0x4
+MD_ENERGY, MD_PAIR_FP64, MD_NO_COMPENSATE, MD_MLP_REUSE = 0x1, 0x2, 0x4, 0x8
 MD_KICK_DRIFT, MD_KICK = 1, 2
 MD_SLICE = 8
 
@@ -41,6 +41,27 @@ class FS(C.Structure):
                 ("c0", C.c_double), ("c1", C.c_double), ("c2", C.c_double)]
 
 
+MD_MLP_IN, MD_MLP_HID, MD_MLP_NPARAM = 16, 64, 5313
+
+
+class MLP(C.Structure):
+    """md_mlp_t: descriptor geometry and input normalisation."""
+    _fields_ = [("rc", C.c_double), ("mu0", C.c_double), ("dmu", C.c_double), ("width", C.c_double),
+                ("mean", C.c_float * MD_MLP_IN), ("inv_std", C.c_float * MD_MLP_IN)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("step", C.c_int64)]
+
+
+def mlp_spec(rc=5.0, mu0=2.0, dmu=0.2, width=0.2, mean=None, inv_std=None) -> MLP:
+    m = MLP(float(rc), float(mu0), float(dmu), float(width))
+    m.mean[:] = [float(v) for v in (np.zeros(MD_MLP_IN) if mean is None else mean)]
+    m.inv_std[:] = [float(v) for v in (np.ones(MD_MLP_IN) if inv_std is None else inv_std)]
+    return m
+
+
 class System(C.Structure):
     """md_system_t of include/md.h."""
     _fields_ = [("box", Box), ("grid", Grid), ("lj", LJ), ("fs", FS),
@@ -54,10 +75,11 @@ class System(C.Structure):
                 ("ws", C.c_void_p), ("ws_bytes", C.c_size_t), ("row_cap", C.c_int32),
                 ("row_cap_needed", C.c_int32), ("potential", C.c_int32), ("flags", C.c_int32),
                 ("need_build", C.c_int32), ("phase", C.c_int32), ("timing", C.c_int32), ("pad_", C.c_int32),
-                ("force_ms", C.c_double), ("force_calls", C.c_int64)]
+                ("force_ms", C.c_double), ("force_calls", C.c_int64),
+                ("mlp", MLP), ("mlp_w", C.c_void_p), ("dEdG", C.c_void_p)]
 
 
-MD_POT_LJ, MD_POT_EAM = 0, 1
+MD_POT_LJ, MD_POT_EAM, MD_POT_MLP = 0, 1, 2
 
 
 class MDError(RuntimeError):
@@ -92,7 +114,19 @@ def lib():
         L.md_forces_lj.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, C.c_int32, _vp, _vp, C.POINTER(LJ),
                                    _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
         L.md_forces_eam.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(FS), _vp,
-                                    _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+                                    _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_mlp_descriptors.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(MLP),
+                                         _vp, _vp]
+        L.md_mlp_eval.argtypes = [C.c_int64, _vp, C.POINTER(MLP), _vp, _vp, _vp, _vp]
+        L.md_forces_mlp.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(MLP), _vp,
+                                    _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_mlp_workspace_bytes.argtypes = [C.c_int64]
+        L.md_mlp_workspace_bytes.restype = C.c_size_t
+        L.md_mlp_moments.argtypes = [C.c_int64, _vp, _vp, _vp, C.c_size_t, _vp]
+        L.md_mlp_grad.argtypes = [C.c_int64, _vp, _vp, _vp, C.POINTER(MLP), _vp, _vp, _vp, _vp, C.c_size_t,
+                                  _vp]
+        L.md_mlp_train_step.argtypes = [C.c_int64, _vp, _vp, _vp, C.POINTER(MLP), C.POINTER(Adam), _vp, _vp,
+                                        _vp, _vp, _vp, _vp, C.c_size_t, _vp]
         L.md_integrate.argtypes = [C.c_int32, C.POINTER(Box), C.c_int64, _vp, _vp, _vp, C.c_double,
                                    C.c_double, C.c_double, _vp, C.c_double, _vp, C.c_int32, _vp, _vp,
                                    C.c_int32, _vp, C.c_size_t, _vp]
@@ -226,15 +260,82 @@ def md_forces_lj(L, n: int, x, xs, row_cap: int, idx, count, lj: tuple, f, ev, f
 
 
 def md_forces_eam(L, n: int, xs, row_cap: int, idx, count, fs: dict, rho, fprime, f, ev, flags: int, ws,
-                  stream=None):
+                  stream=None, e_atom=None):
     import torch
     p = FS(fs["A"], fs["d"], fs["c"], fs["c0"], fs["c1"], fs["c2"])
     _check(lib().md_forces_eam(C.byref(box(L)), int(n), _ptr(xs, torch.int32, 4 * n, "xs"), int(row_cap),
                                _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"),
                                _ptr(count, torch.int32, n, "count"), C.byref(p), _ptr(rho, torch.float32, n, "rho"),
                                _ptr(fprime, torch.float32, n, "fprime"), _ptr(f, torch.float32, 3 * n, "f"),
+                               _ptr(e_atom, torch.float32, n, "e_atom"),
                                _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
                                _stream(stream)), "md_forces_eam")
+
+
+def md_mlp_descriptors(L, n: int, xs, row_cap: int, idx, count, mlp: MLP, G, stream=None):
+    import torch
+    _check(lib().md_mlp_descriptors(C.byref(box(L)), int(n), _ptr(xs, torch.int32, 4 * n, "xs"), int(row_cap),
+                                    _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"),
+                                    _ptr(count, torch.int32, n, "count"), C.byref(mlp),
+                                    _ptr(G, torch.float32, MD_MLP_IN * n, "G"), _stream(stream)),
+           "md_mlp_descriptors")
+
+
+def md_mlp_eval(n: int, G, mlp: MLP, w, e_atom, dEdG=None, stream=None):
+    import torch
+    _check(lib().md_mlp_eval(int(n), _ptr(G, torch.float32, MD_MLP_IN * n, "G"), C.byref(mlp),
+                             _ptr(w, torch.int16, MD_MLP_NPARAM, "w"), _ptr(e_atom, torch.float32, n, "e_atom"),
+                             _ptr(dEdG, torch.float32, MD_MLP_IN * n, "dEdG"), _stream(stream)), "md_mlp_eval")
+
+
+def md_forces_mlp(L, n: int, xs, row_cap: int, idx, count, mlp: MLP, w, dEdG, e_atom, f, ev, flags: int, ws,
+                  stream=None):
+    import torch
+    _check(lib().md_forces_mlp(C.byref(box(L)), int(n), _ptr(xs, torch.int32, 4 * n, "xs"), int(row_cap),
+                               _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"),
+                               _ptr(count, torch.int32, n, "count"), C.byref(mlp),
+                               _ptr(w, torch.int16, MD_MLP_NPARAM, "w"),
+                               _ptr(dEdG, torch.float32, MD_MLP_IN * n, "dEdG"),
+                               _ptr(e_atom, torch.float32, n, "e_atom"), _ptr(f, torch.float32, 3 * n, "f"),
+                               _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
+                               _stream(stream)), "md_forces_mlp")
+
+
+def md_mlp_workspace_bytes(batch: int) -> int:
+    b = lib().md_mlp_workspace_bytes(int(batch))
+    if b == 0:
+        raise MDError(MD_ERR_ARG, "md_mlp_workspace_bytes")
+    return int(b)
+
+
+def md_mlp_moments(n: int, G, moments, tws, stream=None):
+    import torch
+    _check(lib().md_mlp_moments(int(n), _ptr(G, torch.float32, MD_MLP_IN * n, "G"),
+                                _ptr(moments, torch.float64, 2 * MD_MLP_IN, "moments"), _ptr(tws, name="tws"),
+                                tws.numel(), _stream(stream)), "md_mlp_moments")
+
+
+def md_mlp_grad(batch: int, sel, G, target, mlp: MLP, w, grad, loss, tws, stream=None):
+    import torch
+    _check(lib().md_mlp_grad(int(batch), _ptr(sel, torch.int32, batch, "sel"), _ptr(G, torch.float32, None, "G"),
+                             _ptr(target, torch.float32, None, "target"), C.byref(mlp),
+                             _ptr(w, torch.int16, MD_MLP_NPARAM, "w"),
+                             _ptr(grad, torch.float32, MD_MLP_NPARAM, "grad"),
+                             _ptr(loss, torch.float64, 1, "loss"), _ptr(tws, name="tws"), tws.numel(),
+                             _stream(stream)), "md_mlp_grad")
+
+
+def md_mlp_train_step(batch: int, sel, G, target, mlp: MLP, adam: Adam, master, m1, m2, w, loss, tws,
+                      stream=None):
+    import torch
+    _check(lib().md_mlp_train_step(int(batch), _ptr(sel, torch.int32, batch, "sel"),
+                                   _ptr(G, torch.float32, None, "G"), _ptr(target, torch.float32, None, "target"),
+                                   C.byref(mlp), C.byref(adam),
+                                   _ptr(master, torch.float32, MD_MLP_NPARAM, "master"),
+                                   _ptr(m1, torch.float32, MD_MLP_NPARAM, "m1"),
+                                   _ptr(m2, torch.float32, MD_MLP_NPARAM, "m2"),
+                                   _ptr(w, torch.int16, MD_MLP_NPARAM, "w"), _ptr(loss, torch.float64, 1, "loss"),
+                                   _ptr(tws, name="tws"), tws.numel(), _stream(stream)), "md_mlp_train_step")
 
 
 def ell_rows(n: int, row_cap: int, idx, count):

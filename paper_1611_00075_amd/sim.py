@@ -6,6 +6,7 @@ system and sequences the library calls of a step (Sec. 3.3 of the paper):
                                             md_scale_positions,
                                             md_build_neighbors
     forces                               -> md_forces_lj | md_forces_eam
+                                            | md_forces_mlp
     half kick (+ kinetic energy)         -> md_integrate(MD_KICK)
 
 All arithmetic runs in the HIP kernels; this module only allocates torch
@@ -22,13 +23,15 @@ from . import md as M
 class Simulation:
     """One periodic system on one GPU.
 
-    potential: "lj" (params eps, sigma, rc) or "eam" (Finnis-Sinclair dict).
+    potential: "lj" (params eps, sigma, rc), "eam" (Finnis-Sinclair dict) or
+    "mlp" (descriptor geometry and normalisation `mlp`, an md.MLP, and the
+    MD_MLP_NPARAM bfloat16 parameters `mlp_w`, an int16 device tensor).
     Positions and velocities are FP64; forces FP32 (FP64 with pair_fp64).
     Atoms are kept in cell (Morton) order; `ids` maps back to input order.
     """
 
-    def __init__(self, L, x, v, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None, skin=0.3,
-                 dt=0.005, mass=1.0, force_to_accel=1.0, reach=1, pair_fp64=False,
+    def __init__(self, L, x, v, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None, mlp=None, mlp_w=None,
+                 skin=0.3, dt=0.005, mass=1.0, force_to_accel=1.0, reach=1, pair_fp64=False,
                  compensate=True, device="cuda", row_cap=None, list_slack=1.2):
         self.L = np.asarray(L, dtype=np.float64).reshape(3)
         x = np.asarray(x, dtype=np.float64)
@@ -36,7 +39,17 @@ class Simulation:
         self.potential = potential
         self.lj = tuple(float(a) for a in lj)
         self.fs = fs
-        rc = self.lj[2] if potential == "lj" else max(fs["d"], fs["c"])
+        self.mlp, self.mlp_w = mlp, mlp_w
+        if potential == "lj":
+            rc = self.lj[2]
+        elif potential == "eam":
+            rc = max(fs["d"], fs["c"])
+        elif potential == "mlp":
+            if mlp is None or mlp_w is None:
+                raise ValueError("potential 'mlp' needs mlp and mlp_w")
+            rc = float(mlp.rc)
+        else:
+            raise ValueError(f"unknown potential {potential!r}")
         self.rc = rc
         self.skin = float(skin)
         self.r_list = rc + self.skin
@@ -46,8 +59,8 @@ class Simulation:
         self.flags = M.MD_PAIR_FP64 if pair_fp64 else 0
         if not compensate:
             self.flags |= M.MD_NO_COMPENSATE
-        if potential == "eam" and pair_fp64:
-            raise ValueError("the EAM path is FP32 only")
+        if potential != "lj" and pair_fp64:
+            raise ValueError("the EAM and MLP paths are FP32 only")
         self.dev = torch.device(device)
         self.list_slack = float(list_slack)
         d = self.dev
@@ -64,6 +77,9 @@ class Simulation:
         self.f = torch.zeros((3, max(n, 1)), dtype=fdt, device=d)
         self.rho = torch.zeros(max(n, 1), dtype=torch.float32, device=d)
         self.fprime = torch.zeros(max(n, 1), dtype=torch.float32, device=d)
+        self.e_atom = torch.zeros(max(n, 1), dtype=torch.float32, device=d)
+        self.dEdG = (torch.zeros((max(n, 1), M.MD_MLP_IN), dtype=torch.float32, device=d)
+                     if potential == "mlp" else None)
         self.cell = torch.empty(max(n, 1), dtype=torch.int32, device=d)
         self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=d)
         self.cell_start = torch.empty(self.grid.n_cells + 1, dtype=torch.int32, device=d)
@@ -121,14 +137,30 @@ class Simulation:
         """Number of list entries (host sync)."""
         return int(self.count[: self.n].sum()) if self.n else 0
 
-    def compute_forces(self, energy: bool = False):
-        fl = self.flags | (M.MD_ENERGY if energy else 0)
+    def compute_forces(self, energy: bool = False, site: bool = False):
+        """Forces of the current positions; with energy, ev as well; with
+        site (EAM, MLP), the per-atom energies in e_atom."""
+        fl = self.flags | (M.MD_ENERGY if energy or site else 0)
+        ea = self.e_atom if site else None
         if self.potential == "lj":
             M.md_forces_lj(self.L, self.n, self.x, self.xs, self.row_cap, self.idx, self.count, self.lj, self.f,
                            self.ev, fl, self.ws)
-        else:
+        elif self.potential == "eam":
             M.md_forces_eam(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.fs, self.rho,
-                            self.fprime, self.f, self.ev, fl, self.ws)
+                            self.fprime, self.f, self.ev, fl, self.ws, e_atom=ea)
+        else:
+            M.md_forces_mlp(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.mlp, self.mlp_w,
+                            self.dEdG, ea, self.f, self.ev, fl, self.ws)
+
+    def descriptors(self, spec, out=None):
+        """Raw MLP descriptors (n, 16) of the current positions in the
+        sorted atom order (the list cutoff must be >= spec.rc)."""
+        if spec.rc > self.r_list:
+            raise ValueError("descriptor cutoff exceeds the list cutoff")
+        G = out if out is not None else torch.empty((self.n, M.MD_MLP_IN), dtype=torch.float32,
+                                                    device=self.dev)
+        M.md_mlp_descriptors(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, spec, G)
+        return G
 
     def _mark(self, name):
         if self.events is None:
@@ -193,7 +225,9 @@ class Simulation:
         S.status, S.host_status = ptr(self.status), ptr(self._flag_host)
         S.ws, S.ws_bytes = ptr(self.ws), self.ws.numel()
         S.row_cap = self.row_cap
-        S.potential = M.MD_POT_LJ if self.potential == "lj" else M.MD_POT_EAM
+        S.potential = {"lj": M.MD_POT_LJ, "eam": M.MD_POT_EAM, "mlp": M.MD_POT_MLP}[self.potential]
+        if self.potential == "mlp":
+            S.mlp, S.mlp_w, S.dEdG = self.mlp, ptr(self.mlp_w), ptr(self.dEdG)
         S.flags = self.flags
         return S
 
@@ -217,7 +251,7 @@ class Simulation:
 
     def energies(self):
         """(potential, kinetic) of the current state, FP64; potential is
-        E_shift for LJ and E_total for EAM (forces are recomputed)."""
+        E_shift for LJ and E_total for EAM and MLP (forces are recomputed)."""
         self.compute_forces(energy=True)
         M.md_integrate(M.MD_KICK, self.L, self.n, self.x, self.v, self.f, 0.0, self.accel, self.mass,
                        None, 0.0, None, 0, None, self.ke, self.flags & M.MD_PAIR_FP64, self.ws)

@@ -269,9 +269,12 @@ def test_forces_eam_vs_oracle(M, orc):
     rho = torch.zeros(n, dtype=torch.float32, device="cuda")
     fp = torch.zeros(n, dtype=torch.float32, device="cuda")
     ev = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ea = torch.zeros(n, dtype=torch.float32, device="cuda")
     M.md_forces_eam(s.L, n, xsc, st["cap"], st["idx"], st["cnt"], inputs.FS_CU, rho, fp, f, ev, M.MD_ENERGY,
-                    st["ws"])
+                    st["ws"], e_atom=ea)
     p = st["perm"].cpu().numpy()[:n]
+    eg = np.empty(n)
+    eg[p] = ea.cpu().numpy()
     fg = np.empty((n, 3))
     fg[p] = f.cpu().numpy().T
     rg = np.empty(n)
@@ -279,6 +282,8 @@ def test_forces_eam_vs_oracle(M, orc):
     oc, ic = orc.neighbors_cells(x, s.L, r_list)
     r = orc.forces_eam(x, s.L, oc, ic, inputs.FS_CU)
     assert np.abs(rg - r["rho"]).max() / r["rho"].max() < 1e-5
+    # site energies F(rho_i) + 1/2 sum_j V(r_ij): FP32 values of ~3.5 eV
+    assert np.abs(eg - r["e_atom"]).max() < 2e-6 * np.abs(r["e_atom"]).max()
     err = np.linalg.norm(fg - r["f"]) / np.linalg.norm(r["f"])
     print(f"EAM FP32 force error (normwise) {err:.3e}")
     assert err < 1e-5, err
