@@ -30,6 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed instructions: 256 CUs x 64 lanes x 2 (FMA)
+# x 2.4 GHz (the packed form, which doubles it, is not used on this platform)
+FP32_VALU_PEAK_TFLOPS = 78.6
 
 
 def recorded_traffic(key):
@@ -90,13 +93,129 @@ def eam_force_bytes(n_atoms, n_entries):
     return 2 * 4 * n_entries + (2 * 4 + 2 * 16 + 12 + 12) * n_atoms
 
 
+def mlp_force_flops(n_atoms, n_in, n_entries):
+    """Algorithmic FP32 operations of the two MLP force passes (FMA = 2).
+    Both passes test every listed pair against the cutoff (7).  Per pair
+    within the descriptor cutoff, pass 1 forms the 16 Gaussians from three
+    exponentials (37), the cutoff function (16) and the 16 descriptor sums
+    (32); pass 2 the Gaussians, the cutoff and its derivative (52), the 16
+    coefficients and the two weighted sums over them (80) and the force and
+    its accumulation (10).  Per atom, pass 1 runs the network forward and
+    backward on the matrix cores: 4 x 5,120 multiply-adds = 20,480 BF16
+    operations.  Returns (pass-1 VALU, pass-2 VALU, pass-1 matrix)."""
+    return (7 * n_entries + 85 * n_in, 7 * n_entries + 186 * n_in, 20480 * n_atoms)
+
+
+def mlp_leg(torch, steps, warmup, n_snap, epochs, f_eam0):
+    """Learned potential (Cu surrogate): training data from the GPU's own
+    EAM trajectories, training on the GPU, then the 4 M-atom crystal of the
+    EAM workload run with MLP forces."""
+    from paper_1611_00075_amd import inputs, md as M
+    from paper_1611_00075_amd import mlp as P
+    from paper_1611_00075_amd.sim import Simulation
+    out = {}
+    t0 = time.perf_counter()
+    temps = P.training_temperatures()
+    keep = n_snap - n_snap // 10
+    snaps = [P.eam_trajectory(float(T), n_snap, seed=3000 + k, keep_from=keep) for k, T in enumerate(temps)]
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    Gtr, etr, Gte, ete = P.split(snaps)
+    mean, inv = P.normalisation(Gtr)
+    sp = P.spec(mean, inv)
+    tr = P.Trainer(Gtr, etr, sp, P.init_params(5, e_mean=float(etr.double().mean())), batch=4096, seed=5)
+    t1 = time.perf_counter()
+    hist = tr.fit(epochs, lr=3e-3, lr_min=3e-5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    pot = tr.potential
+    e_rmse = P.rmse(P.predict(Gte, pot), ete)
+    fe, fm = [], []
+    for sn in snaps:
+        for k in range(0, len(sn.x), 5):
+            fe.append(sn.f[k])
+            fm.append(P.mlp_forces(pot, sn.L, sn.x[k]))
+    fe, fm = np.concatenate(fe), np.concatenate(fm)
+    out["training"] = {
+        "snapshots": int(sum(s.G.shape[0] for s in snaps)), "atoms_per_snapshot": int(snaps[0].G.shape[1]),
+        "temperatures_K": [float(temps[0]), float(temps[-1]), len(temps)],
+        "train_rows": int(Gtr.shape[0]), "test_rows": int(Gte.shape[0]), "epochs": epochs, "batch": 4096,
+        "steps": tr.step, "data_seconds": t_data, "train_seconds": t_train,
+        "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+        "heldout_energy_rmse_eV": e_rmse,
+        "heldout_force_rmse_eV_A": float(np.sqrt(np.mean((fm - fe) ** 2))),
+        "heldout_force_rms_eam_eV_A": float(np.sqrt(np.mean(fe ** 2))),
+    }
+    del snaps, Gtr, etr, Gte, ete
+    torch.cuda.empty_cache()
+    # the 4 M-atom crystal with MLP forces
+    s = inputs.eam_cu()
+    sim = Simulation(s.L, s.x, s.v, potential="mlp", mlp=sp, mlp_w=pot.w, skin=1.0, dt=1.0,
+                     mass=inputs.CU_MASS_AMU, force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
+    f0 = sim.forces().astype(np.float64)
+    frmse = float(np.sqrt(np.mean((f0 - f_eam0) ** 2))) if f_eam0 is not None else None
+    ep0, ek0 = sim.energies()
+    r = run_workload(sim, steps, warmup, torch)
+    ep1, ek1 = sim.energies()
+    # pass 2 alone (dE/dG reused), then both passes, timed with HIP events
+    n = s.n
+    st = torch.cuda.current_stream()
+    ms = {}
+    for name, fl in (("pass2", M.MD_MLP_REUSE), ("both", 0)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        M.md_forces_mlp(sim.L, n, sim.xs, sim.row_cap, sim.idx, sim.count, sim.mlp, sim.mlp_w, sim.dEdG, None,
+                        sim.f, sim.ev, fl, sim.ws)
+        a.record(st)
+        for _ in range(10):
+            M.md_forces_mlp(sim.L, n, sim.xs, sim.row_cap, sim.idx, sim.count, sim.mlp, sim.mlp_w, sim.dEdG, None,
+                            sim.f, sim.ev, fl, sim.ws)
+        b.record(st)
+        torch.cuda.synchronize()
+        ms[name] = a.elapsed_time(b) / 10
+    entries = sim.n_pairs
+    within = pairs_within(sim, float(sp.rc), torch)
+    v1, v2, mfma = mlp_force_flops(n, within, entries)
+    out.update({
+        "atoms": n, "steps": steps, "value": n * steps / r["seconds"], "unit": "atom-steps/s",
+        "ms_per_step": 1e3 * r["seconds"] / steps, "rebuilds": r["rebuilds"], "forces_ms": r["force_ms"],
+        "pass1_ms": ms["both"] - ms["pass2"], "pass2_ms": ms["pass2"], "list_entries": entries,
+        "force_rmse_vs_eam_eV_A": frmse,
+        "force_rms_eam_eV_A": float(np.sqrt(np.mean(f_eam0 ** 2))) if f_eam0 is not None else None,
+        "energy_drift_eV_per_atom": ((ep1 + ek1) - (ep0 + ek0)) / n,
+        "pairs_within_rc": within, "pass1_valu_flops": v1, "pass2_valu_flops": v2, "pass1_mfma_flops": mfma,
+        "phases_ms_per_call_api": {k: v[0] for k, v in r["phases"].items()},
+    })
+    return out, sim
+
+
+def pairs_within(sim, rc, torch, chunk=131072):
+    """Number of list entries closer than rc (a measurement aid: torch
+    gathers over the sliced-ELL rows, chunk by chunk)."""
+    from paper_1611_00075_amd import md as M
+    n, cap = sim.n, sim.row_cap
+    rows = sim.idx[: M.ell_size(n, cap)].view(-1, cap // 8, 8, 8).permute(0, 2, 1, 3).reshape(-1, cap)[:n]
+    cnt = sim.count[:n]
+    L = torch.tensor(sim.L, dtype=torch.float64, device=sim.x.device).view(3, 1, 1)
+    total = 0
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        r = rows[a:b].long()
+        valid = torch.arange(cap, device=r.device)[None, :] < cnt[a:b, None]
+        d = sim.x[:, r.clamp_(0, n - 1)] - sim.x[:, a:b, None]
+        d -= L * torch.round(d / L)
+        total += int(((d * d).sum(0) < rc * rc).logical_and_(valid).sum())
+    return total
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="all", choices=["all", "lj"])
+    ap.add_argument("--only", default="all", choices=["all", "lj", "mlp"])
+    ap.add_argument("--mlp-snapshots", type=int, default=1250, help="snapshots per temperature (16 temperatures)")
+    ap.add_argument("--mlp-epochs", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -149,25 +268,29 @@ def main():
     del sim
     torch.cuda.empty_cache()
 
-    if args.only == "all":
-        extra = {}
+    extra = {}
+    f_eam0 = None
+    if args.only in ("all", "mlp"):
         # ---- EAM metal, 4 M atoms ----------------------------------------
         s3 = inputs.eam_cu()
         sim3 = Simulation(s3.L, s3.x, s3.v, potential="eam", fs=inputs.FS_CU, skin=1.0, dt=1.0,
                           mass=inputs.CU_MASS_AMU, force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
-        st3 = 200
-        r3 = run_workload(sim3, st3, 10, torch)
-        f3 = r3["force_ms"]
-        b3 = eam_force_bytes(s3.n, sim3.n_pairs)
-        extra["eam_cu_fcc_100^3"] = {
-            "atoms": s3.n, "steps": st3, "value": s3.n * st3 / r3["seconds"], "unit": "atom-steps/s",
-            "ms_per_step": 1e3 * r3["seconds"] / st3, "rebuilds": r3["rebuilds"],
-            "forces_ms": f3, "forces_GBs": b3 / (f3 * 1e-3) / 1e9,
-            "forces_frac_hbm": b3 / (f3 * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "phases_ms_per_call_api": {k: v[0] for k, v in r3["phases"].items()},
-        }
+        f_eam0 = sim3.forces().astype(np.float64)
+        if args.only == "all":
+            st3 = 200
+            r3 = run_workload(sim3, st3, 10, torch)
+            f3 = r3["force_ms"]
+            b3 = eam_force_bytes(s3.n, sim3.n_pairs)
+            extra["eam_cu_fcc_100^3"] = {
+                "atoms": s3.n, "steps": st3, "value": s3.n * st3 / r3["seconds"], "unit": "atom-steps/s",
+                "ms_per_step": 1e3 * r3["seconds"] / st3, "rebuilds": r3["rebuilds"],
+                "forces_ms": f3, "forces_GBs": b3 / (f3 * 1e-3) / 1e9,
+                "forces_frac_hbm": b3 / (f3 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "phases_ms_per_call_api": {k: v[0] for k, v in r3["phases"].items()},
+            }
         del sim3
         torch.cuda.empty_cache()
+    if args.only == "all":
         # ---- LJ crystal, 4,000 atoms, FP64 (launch-bound) -------------------
         s1 = inputs.lj_fcc()
         sim1 = Simulation(s1.L, s1.x, s1.v, skin=0.3, dt=0.005, pair_fp64=True)
@@ -177,6 +300,23 @@ def main():
             "ms_per_step": 1e3 * r1["seconds"] / 100,
         }
         del sim1
+    if args.only in ("all", "mlp"):
+        # ---- learned potential: train on the GPU, run the 4 M-atom crystal --
+        m, simm = mlp_leg(torch, 200, 10, args.mlp_snapshots, args.mlp_epochs, f_eam0)
+        del simm
+        eam = extra.get("eam_cu_fcc_100^3")
+        m["vs_eam"] = m["value"] / eam["value"] if eam else None
+        k2 = m["pass2_ms"] >= m["pass1_ms"]
+        t_ms = m["pass2_ms"] if k2 else m["pass1_ms"]
+        fl = m["pass2_valu_flops"] if k2 else m["pass1_valu_flops"]
+        m["roofline"] = {
+            "bound": "alu", "kernel": "k_mlp_force (pass 2)" if k2 else "k_mlp_atoms (pass 1)",
+            "achieved": fl / (t_ms * 1e-3) / 1e12, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": fl / (t_ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+            "launch_ms": t_ms,
+        }
+        extra["mlp_cu_fcc_100^3"] = m
+    if extra:
         result["extra"] = extra
 
     if not args.no_cpu_baseline:

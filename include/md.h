@@ -281,7 +281,8 @@ int md_mlp_moments(int64_t n, const float *G, double *moments, void *tws,
                    size_t tws_bytes, void *stream);
 
 /* Per-atom energy loss of a batch, L = (1/B) sum_b (E(G[sel[b]]) -
- * target[sel[b]])^2 (sel may be NULL: rows 0..B-1), and its gradient with
+ * target[sel[b]])^2 (sel may be NULL: rows 0..B-1; its entries must index
+ * rows of G and target, which the library cannot check), and its gradient with
  * respect to the parameters (float[MD_MLP_NPARAM], the layout of w) by back
  * propagation: BF16 matrix-core products for dL/dW1, dL/dW2 and the
  * backward pass, FP32 sums for the biases and w3, per-block partials summed

@@ -40,6 +40,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kIn = MD_MLP_IN, kHid = MD_MLP_HID, kNP = MD_MLP_NPARAM;
 constexpr int oW1 = 0, oB1 = oW1 + kHid * kIn, oW2 = oB1 + kHid, oB2 = oW2 + kHid * kHid, oW3 = oB2 + kHid,
@@ -61,15 +62,20 @@ __device__ __forceinline__ f32x4 mfma(const bf16x8 &a, const bf16x8 &b, const f3
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 __device__ __forceinline__ uint16_t f_to_bf16(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 
+// Float -> bfloat16 (round to nearest even, v_cvt_pk_bf16_f32).  Vectors of
+// bf16 are only ever built whole by a vector conversion: element-wise
+// reads and writes of bf16 vectors are avoided (this compiler folds such
+// sequences wrongly).
 __device__ __forceinline__ bf16x8 pack(const f32x4 &lo, const f32x4 &hi)
 {
-    bf16x8 r;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        r[j] = (__bf16)lo[j];
-        r[4 + j] = (__bf16)hi[j];
-    }
-    return r;
+    const f32x8 v = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    return __builtin_convertvector(v, bf16x8);
+}
+
+__device__ __forceinline__ bf16x8 pack8(const float (&u)[8])
+{
+    const f32x8 v = {u[0], u[1], u[2], u[3], u[4], u[5], u[6], u[7]};
+    return __builtin_convertvector(v, bf16x8);
 }
 
 __device__ __forceinline__ float sigm(float a)
@@ -203,6 +209,7 @@ __device__ __forceinline__ bf16x8 op(const WeightsLds &L, int o, int lane)
 
 struct Fwd {
     f32x4 a1[4], a2[4];     // pre-activations of lane's atom, features 16t + 4g + r
+    f32x4 h[4];             // silu(a1) before rounding
     bf16x8 h1[2];           // layer-2 B operand
     float E;                // energy of atom lane % 16
 };
@@ -217,13 +224,12 @@ __device__ __forceinline__ void forward(const WeightsLds &L, int lane, const bf1
 #pragma unroll
         for (int r = 0; r < 4; ++r) F.a1[t][r] += L.b1[16 * t + 4 * g + r];
     }
-    f32x4 h[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) h[t][r] = F.a1[t][r] * sigm(F.a1[t][r]);
-    F.h1[0] = pack(h[0], h[1]);
-    F.h1[1] = pack(h[2], h[3]);
+        for (int r = 0; r < 4; ++r) F.h[t][r] = F.a1[t][r] * sigm(F.a1[t][r]);
+    F.h1[0] = pack(F.h[0], F.h[1]);
+    F.h1[1] = pack(F.h[2], F.h[3]);
     float e = 0.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -373,9 +379,11 @@ __global__ __launch_bounds__(kBlock) void k_mlp_atoms(int64_t n, MlpArgs p, cons
             if (g < 2 && i < n) {
                 const float4 u0 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g);
                 const float4 u1 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g + 4);
-                const float u[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+                const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+                float u[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) X[j] = (__bf16)((u[j] - L.mean[8 * g + j]) * L.inv_std[8 * g + j]);
+                for (int j = 0; j < 8; ++j) u[j] = (v[j] - L.mean[8 * g + j]) * L.inv_std[8 * g + j];
+                X = pack8(u);
             }
         }
         if (NET) {
@@ -554,15 +562,17 @@ __global__ __launch_bounds__(kBlock) void k_mlp_grad(int64_t batch, const int32_
             const int64_t row = valid ? (sel ? int64_t(sel[a]) : a) : 0;
             bf16x8 X = {};
             if (g < 2) {
+                float u[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 if (valid) {
                     const float4 u0 = *reinterpret_cast<const float4 *>(G + row * kIn + 8 * g);
                     const float4 u1 = *reinterpret_cast<const float4 *>(G + row * kIn + 8 * g + 4);
-                    const float u[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+                    const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) X[j] = (__bf16)((u[j] - L.mean[8 * g + j]) * L.inv_std[8 * g + j]);
+                    for (int j = 0; j < 8; ++j) u[j] = (v[j] - L.mean[8 * g + j]) * L.inv_std[8 * g + j];
                 }
+                X = pack8(u);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) T.xT[8 * g + j][h * kTile + m] = __builtin_bit_cast(uint16_t, X[j]);
+                for (int j = 0; j < 8; ++j) T.xT[8 * g + j][h * kTile + m] = f_to_bf16(u[j]);
             }
             Fwd F;
             forward(L, lane, X, F);
@@ -583,7 +593,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_grad(int64_t batch, const int32_
                     d[t][r] = gE * L.w3[f] * (s2 * __builtin_fmaf(a2, 1.f - s2, 1.f));
                     gb2[4 * t + r] += d[t][r];
                     T.d2T[f][h * kTile + m] = f_to_bf16(d[t][r]);
-                    T.h1T[f][h * kTile + m] = __builtin_bit_cast(uint16_t, F.h1[t >> 1][4 * (t & 1) + r]);
+                    T.h1T[f][h * kTile + m] = f_to_bf16(F.h[t][r]);
                 }
             const bf16x8 D2[2] = {pack(d[0], d[1]), pack(d[2], d[3])};
 #pragma unroll

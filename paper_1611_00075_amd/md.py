@@ -315,8 +315,19 @@ def md_mlp_moments(n: int, G, moments, tws, stream=None):
                                 tws.numel(), _stream(stream)), "md_mlp_moments")
 
 
+def _batch_rows(batch: int, sel, G, target):
+    """Rows of G / target a batch reads: sel[:batch] (whose entries must
+    index rows of both) or rows 0..batch-1."""
+    rows = min(G.numel() // MD_MLP_IN, target.numel())
+    if sel is None and rows < batch:
+        raise ValueError(f"batch of {batch} rows, G/target hold {rows}")
+    if sel is not None and sel.numel() < batch:
+        raise ValueError(f"sel holds {sel.numel()} of {batch} entries")
+
+
 def md_mlp_grad(batch: int, sel, G, target, mlp: MLP, w, grad, loss, tws, stream=None):
     import torch
+    _batch_rows(batch, sel, G, target)
     _check(lib().md_mlp_grad(int(batch), _ptr(sel, torch.int32, batch, "sel"), _ptr(G, torch.float32, None, "G"),
                              _ptr(target, torch.float32, None, "target"), C.byref(mlp),
                              _ptr(w, torch.int16, MD_MLP_NPARAM, "w"),
@@ -328,6 +339,7 @@ def md_mlp_grad(batch: int, sel, G, target, mlp: MLP, w, grad, loss, tws, stream
 def md_mlp_train_step(batch: int, sel, G, target, mlp: MLP, adam: Adam, master, m1, m2, w, loss, tws,
                       stream=None):
     import torch
+    _batch_rows(batch, sel, G, target)
     _check(lib().md_mlp_train_step(int(batch), _ptr(sel, torch.int32, batch, "sel"),
                                    _ptr(G, torch.float32, None, "G"), _ptr(target, torch.float32, None, "target"),
                                    C.byref(mlp), C.byref(adam),

@@ -197,10 +197,11 @@ def equilibrate(sim: Simulation, T: float, steps: int, rescale_every: int):
 
 
 def eam_trajectory(T: float, n_snap: int, *, seed: int, sample_every: int = 20, equil_steps: int = 2000,
-                   rescale_every: int = 100, ncell: int = 4, keep: bool = False) -> Snapshots:
+                   rescale_every: int = 100, ncell: int = 4, keep_from: int | None = None) -> Snapshots:
     """One Cu trajectory at temperature T on the GPU: equilibration with
     velocity rescaling, then n_snap NVE snapshots every `sample_every` fs with
-    their descriptors and site energies."""
+    their descriptors and site energies; positions and EAM forces of the
+    snapshots from index keep_from on are copied to the host."""
     s = inputs.eam_cu(ncell=ncell, T=T, seed=seed)
     sim = eam_simulation(s)
     equilibrate(sim, T, equil_steps, rescale_every)
@@ -215,10 +216,10 @@ def eam_trajectory(T: float, n_snap: int, *, seed: int, sample_every: int = 20, 
         sim.descriptors(sp, out=G[k])
         sim.compute_forces(site=True)
         E[k].copy_(sim.e_atom[:n])
-        if keep:
+        if keep_from is not None and k >= keep_from:
             xs.append(sim.x[:, :n].T.cpu().numpy())
             fs.append(sim.f[:, :n].T.double().cpu().numpy())
-    return Snapshots(T, s.L.copy(), G, E, np.stack(xs) if keep else None, np.stack(fs) if keep else None)
+    return Snapshots(T, s.L.copy(), G, E, np.stack(xs) if xs else None, np.stack(fs) if fs else None)
 
 
 def training_temperatures(k: int = 16, lo: float = 300.0, hi: float = 1200.0) -> np.ndarray:

@@ -250,13 +250,15 @@ class Simulation:
         return S.force_ms, S.force_calls
 
     def energies(self):
-        """(potential, kinetic) of the current state, FP64; potential is
-        E_shift for LJ and E_total for EAM and MLP (forces are recomputed)."""
+        """(potential, kinetic) of the current state, FP64, both in the
+        potential's energy unit (the kinetic energy 1/2 m v^2 divided by
+        force_to_accel); potential is E_shift for LJ and E_total for EAM and
+        MLP (forces are recomputed)."""
         self.compute_forces(energy=True)
         M.md_integrate(M.MD_KICK, self.L, self.n, self.x, self.v, self.f, 0.0, self.accel, self.mass,
                        None, 0.0, None, 0, None, self.ke, self.flags & M.MD_PAIR_FP64, self.ws)
         ev = self.ev.cpu().numpy()
-        ke = float(self.ke.cpu()[0])
+        ke = float(self.ke.cpu()[0]) / self.k
         return (ev[1] if self.potential == "lj" else ev[0]), ke
 
     def by_id(self, t, ncomp=3):

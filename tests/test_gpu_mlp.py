@@ -124,7 +124,7 @@ def test_descriptors_perfect_lattice_uniform(M, om):
 @pytest.mark.parametrize("n", [1000, 16, 1, 0])
 def test_network_vs_oracle(M, orc, om, n):
     from paper_1611_00075_amd import mlp as P
-    x, L = _system(5, 6)
+    x, L = _system(5, 7)
     x = orc.wrap(x, L)
     off, idx = orc.neighbors_brute(x, L, 6.0)
     G32 = om.descriptors(x, L, off, idx, om.Spec())[:n].astype(np.float32)
@@ -222,7 +222,7 @@ def test_forces_deterministic_and_md_run_path(M, orc, om):
 @pytest.mark.parametrize("batch,use_sel", [(1000, True), (4096, False), (37, True)])
 def test_gradient_vs_oracle(M, orc, om, batch, use_sel):
     from paper_1611_00075_amd import mlp as P
-    x, L = _system(14, 8)
+    x, L = _system(14, 11)
     x = orc.wrap(x, L)
     off, idx = orc.neighbors_brute(x, L, 6.0)
     G32 = om.descriptors(x, L, off, idx, om.Spec()).astype(np.float32)

@@ -70,7 +70,7 @@ def trained(M, data):
     master = P.init_params(7, e_mean=float(etr.double().mean()))
     tr = P.Trainer(Gtr, etr, sp, master, batch=4096, seed=7)
     untrained = P.Potential(sp, tr.w.clone())
-    hist = tr.fit(60, lr=3e-3, lr_min=3e-5)
+    hist = tr.fit(600, lr=1e-2, lr_min=1e-4)
     return dict(pot=tr.potential, untrained=untrained, hist=hist, mean=mean, inv=inv)
 
 

@@ -410,10 +410,10 @@ def test_md_run_eam_energy_conservation(M, orc):
     e = []
     for k in range(5):
         ep, ek = sim.energies()
-        e.append(ep + ek * inputs.AMU_A2_FS2_IN_EV)
+        e.append(ep + ek)
         sim.run(20)
     ep, ek = sim.energies()
-    e.append(ep + ek * inputs.AMU_A2_FS2_IN_EV)
+    e.append(ep + ek)
     a = orc.md_run(s.x.copy(), s.v.copy(), s.L, 100, potential="eam", fs=inputs.FS_CU, r_list=5.4, skin=1.0,
                    dt=1.0, mass=inputs.CU_MASS_AMU, force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
     eo = a["epot"] + a["ekin"] * inputs.AMU_A2_FS2_IN_EV
