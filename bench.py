@@ -37,17 +37,24 @@ FP32_VALU_PEAK_TFLOPS = 78.6
 
 def recorded_traffic(key):
     """HBM bytes per launch from the committed rocprofv3 counter runs
-    (profiles/traffic.json), or None when the kernel source has changed
+    (profiles/traffic.json), or None when a source of the kernel has changed
     since the counters were taken."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
     except (OSError, KeyError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+    if h.hexdigest() != rec["sources_sha256"]:
         return None
     return rec["traffic_bytes"]
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def _phase_ms(sim):
@@ -106,7 +113,7 @@ def mlp_force_flops(n_atoms, n_in, n_entries):
     return (7 * n_entries + 85 * n_in, 7 * n_entries + 186 * n_in, 20480 * n_atoms)
 
 
-def mlp_leg(torch, steps, warmup, n_snap, epochs, f_eam0):
+def mlp_leg(torch, steps, warmup, n_snap, epochs, equil, thermal):
     """Learned potential (Cu surrogate): training data from the GPU's own
     EAM trajectories, training on the GPU, then the 4 M-atom crystal of the
     EAM workload run with MLP forces."""
@@ -116,10 +123,12 @@ def mlp_leg(torch, steps, warmup, n_snap, epochs, f_eam0):
     out = {}
     t0 = time.perf_counter()
     temps = P.training_temperatures()
-    keep = n_snap - n_snap // 10
-    snaps = [P.eam_trajectory(float(T), n_snap, seed=3000 + k, keep_from=keep) for k, T in enumerate(temps)]
+    keep = n_snap - max(1, n_snap // 10)
+    snaps = [P.eam_trajectory(float(T), n_snap, seed=3000 + k, keep_from=keep, equil_steps=equil)
+             for k, T in enumerate(temps)]
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
+    log(f"MLP: data in {t_data:.1f} s, training")
     Gtr, etr, Gte, ete = P.split(snaps)
     mean, inv = P.normalisation(Gtr)
     sp = P.spec(mean, inv)
@@ -149,11 +158,16 @@ def mlp_leg(torch, steps, warmup, n_snap, epochs, f_eam0):
     del snaps, Gtr, etr, Gte, ete
     torch.cuda.empty_cache()
     # the 4 M-atom crystal with MLP forces
+    log(f"MLP: trained in {t_train:.1f} s; 4 M-atom run")
     s = inputs.eam_cu()
     sim = Simulation(s.L, s.x, s.v, potential="mlp", mlp=sp, mlp_w=pot.w, skin=1.0, dt=1.0,
                      mass=inputs.CU_MASS_AMU, force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
-    f0 = sim.forces().astype(np.float64)
-    frmse = float(np.sqrt(np.mean((f0 - f_eam0) ** 2))) if f_eam0 is not None else None
+    # forces on a thermalised configuration of the EAM run
+    x_th, f_th, T_th = thermal
+    f_m = P.mlp_forces(pot, s.L, x_th)
+    frmse = float(np.sqrt(np.mean((f_m - f_th) ** 2)))
+    frms = float(np.sqrt(np.mean(f_th ** 2)))
+    del f_m
     ep0, ek0 = sim.energies()
     r = run_workload(sim, steps, warmup, torch)
     ep1, ek1 = sim.energies()
@@ -179,8 +193,8 @@ def mlp_leg(torch, steps, warmup, n_snap, epochs, f_eam0):
         "atoms": n, "steps": steps, "value": n * steps / r["seconds"], "unit": "atom-steps/s",
         "ms_per_step": 1e3 * r["seconds"] / steps, "rebuilds": r["rebuilds"], "forces_ms": r["force_ms"],
         "pass1_ms": ms["both"] - ms["pass2"], "pass2_ms": ms["pass2"], "list_entries": entries,
-        "force_rmse_vs_eam_eV_A": frmse,
-        "force_rms_eam_eV_A": float(np.sqrt(np.mean(f_eam0 ** 2))) if f_eam0 is not None else None,
+        "force_rmse_vs_eam_eV_A": frmse, "force_rms_eam_eV_A": frms,
+        "force_config": f"EAM trajectory of the same crystal after its timed steps, T = {T_th:.0f} K",
         "energy_drift_eV_per_atom": ((ep1 + ek1) - (ep0 + ek0)) / n,
         "pairs_within_rc": within, "pass1_valu_flops": v1, "pass2_valu_flops": v2, "pass1_mfma_flops": mfma,
         "phases_ms_per_call_api": {k: v[0] for k, v in r["phases"].items()},
@@ -216,6 +230,8 @@ def main():
     ap.add_argument("--only", default="all", choices=["all", "lj", "mlp"])
     ap.add_argument("--mlp-snapshots", type=int, default=1250, help="snapshots per temperature (16 temperatures)")
     ap.add_argument("--mlp-epochs", type=int, default=20)
+    ap.add_argument("--mlp-equil", type=int, default=2000, help="equilibration steps per temperature")
+    ap.add_argument("--mlp-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -228,9 +244,11 @@ def main():
     from paper_1611_00075_amd.sim import Simulation
 
     torch.cuda.set_device(0)
+    log("LJ void system: generating")
     # ---- headline: LJ with voids ------------------------------------------
     s = inputs.lj_voids()
     sim = Simulation(s.L, s.x, s.v, skin=0.3, dt=0.005)
+    log(f"LJ void system: {s.n} atoms, running")
     r = run_workload(sim, args.steps, args.warmup, torch)
     n = s.n
     value = n * args.steps / r["seconds"]
@@ -269,13 +287,15 @@ def main():
     torch.cuda.empty_cache()
 
     extra = {}
-    f_eam0 = None
+    thermal = None
     if args.only in ("all", "mlp"):
         # ---- EAM metal, 4 M atoms ----------------------------------------
+        log("EAM crystal: generating")
         s3 = inputs.eam_cu()
         sim3 = Simulation(s3.L, s3.x, s3.v, potential="eam", fs=inputs.FS_CU, skin=1.0, dt=1.0,
                           mass=inputs.CU_MASS_AMU, force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
-        f_eam0 = sim3.forces().astype(np.float64)
+        if args.only == "mlp":
+            sim3.run(100)
         if args.only == "all":
             st3 = 200
             r3 = run_workload(sim3, st3, 10, torch)
@@ -288,10 +308,14 @@ def main():
                 "forces_frac_hbm": b3 / (f3 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "phases_ms_per_call_api": {k: v[0] for k, v in r3["phases"].items()},
             }
+        _, ke3 = sim3.energies()
+        thermal = (sim3.positions(), sim3.forces().astype(np.float64),
+                   2.0 * ke3 / ((3 * s3.n - 3) * inputs.KB_EV))
         del sim3
         torch.cuda.empty_cache()
     if args.only == "all":
         # ---- LJ crystal, 4,000 atoms, FP64 (launch-bound) -------------------
+        log("LJ crystal FP64")
         s1 = inputs.lj_fcc()
         sim1 = Simulation(s1.L, s1.x, s1.v, skin=0.3, dt=0.005, pair_fp64=True)
         r1 = run_workload(sim1, 100, 10, torch)
@@ -302,7 +326,9 @@ def main():
         del sim1
     if args.only in ("all", "mlp"):
         # ---- learned potential: train on the GPU, run the 4 M-atom crystal --
-        m, simm = mlp_leg(torch, 200, 10, args.mlp_snapshots, args.mlp_epochs, f_eam0)
+        log("MLP: EAM training data")
+        m, simm = mlp_leg(torch, args.mlp_steps, 10, args.mlp_snapshots, args.mlp_epochs, args.mlp_equil,
+                          thermal)
         del simm
         eam = extra.get("eam_cu_fcc_100^3")
         m["vs_eam"] = m["value"] / eam["value"] if eam else None
@@ -312,7 +338,8 @@ def main():
         m["roofline"] = {
             "bound": "alu", "kernel": "k_mlp_force (pass 2)" if k2 else "k_mlp_atoms (pass 1)",
             "achieved": fl / (t_ms * 1e-3) / 1e12, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": fl / (t_ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+            "frac": fl / (t_ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS,
+            "traffic": recorded_traffic("k_mlp_force_cu_4M" if k2 else "k_mlp_atoms_cu_4M"),
             "launch_ms": t_ms,
         }
         extra["mlp_cu_fcc_100^3"] = m
@@ -320,6 +347,7 @@ def main():
         result["extra"] = extra
 
     if not args.no_cpu_baseline:
+        log("CPU baseline (oracle)")
         import oracle
         k = args.cpu_steps
         ro = oracle.md_run(s.x.copy(), s.v.copy(), s.L, k, r_list=2.8, skin=0.3, dt=0.005)
