@@ -236,11 +236,16 @@ typedef struct md_mlp {
     float inv_std[MD_MLP_IN];
 } md_mlp_t;
 
+/* Longest list row (row_cap) the descriptor passes accept: the in-range
+ * distances of a row are staged in LDS. */
+#define MD_MLP_MAX_ROW 256
+
 /* Raw descriptors G[n][16] (float, row i contiguous) from a full list at
- * any list cutoff >= rc (the output of md_build_neighbors) and the scaled
- * coordinates xs of md_scale_positions.  FP32; the 16 Gaussians of a pair
- * are formed from three exponentials by their ratio recurrence (exact up to
- * rounding for r > 1 A with the default centres and width). */
+ * any list cutoff >= rc (the output of md_build_neighbors, row_cap <=
+ * MD_MLP_MAX_ROW) and the scaled coordinates xs of md_scale_positions.
+ * FP32; the 16 Gaussians of a pair are formed from three exponentials by
+ * their ratio recurrence (exact up to rounding for r > 1 A with the default
+ * centres and width). */
 int md_mlp_descriptors(const md_box_t *box, int64_t n, const uint32_t *xs,
                        int32_t row_cap, const int32_t *idx,
                        const int32_t *count, const md_mlp_t *mlp, float *G,
@@ -251,24 +256,32 @@ int md_mlp_descriptors(const md_box_t *box, int64_t n, const uint32_t *xs,
 int md_mlp_eval(int64_t n, const float *G, const md_mlp_t *mlp,
                 const uint16_t *w, float *e_atom, float *dEdG, void *stream);
 
-/* Forces of the learned potential in two passes over the full list (the
- * same two-pass shape as md_forces_eam):
- *   pass 1: G_i, the network and its backward pass to dE_i/dG_i, stored in
- *           dEdG[n][16] (caller-owned float scratch);
- *   pass 2: F_i = -sum_{j, r_ij < rc} s_ij (r_i - r_j) / r_ij with
- *           s_ij = sum_k (dE_i/dG_ik + dE_j/dG_jk) g_k'(r_ij).
+/* Forces of the learned potential in two passes (the same two-pass shape
+ * as md_forces_eam):
+ *   pass 1: over the full list (row_cap <= MD_MLP_MAX_ROW): G_i, the network
+ *           and its backward pass to dE_i/dG_i, stored in dEdG[n][16]
+ *           (caller-owned float scratch); the pairs within rc are written as
+ *           a compact list in the same sliced-ELL layout, idx_in (as large
+ *           as idx) and cnt_in[n] (caller-owned int32 scratch);
+ *   pass 2: over the compact list, F_i = -sum_{j, r_ij < rc} s_ij
+ *           (r_i - r_j) / r_ij with s_ij = sum_k (dE_i/dG_ik + dE_j/dG_jk)
+ *           g_k'(r_ij).
  * f is float[3n], overwritten; compensated FP32 sums.  e_atom (may be NULL)
  * receives E_i.  With MD_ENERGY, ev[8] = E, E, W_xx, W_yy, W_zz, W_xy, W_xz,
  * W_yz (W_ab = -1/2 sum_i sum_j s_ij R_a R_b / r_ij), FP64 in fixed order.
- * With MD_MLP_REUSE, pass 1 is skipped and dEdG is taken as given (the
- * stored result of an earlier call on the same positions, or the caller's
- * own); w and e_atom are then unused and E in ev is 0.
+ * With MD_MLP_REUSE, pass 1 is skipped, dEdG is taken as given (the stored
+ * result of an earlier call on the same positions, or the caller's own) and
+ * pass 2 walks (row_cap, idx, count) as passed: the full list, or the
+ * compact list idx_in/cnt_in of an earlier call on the same positions; w,
+ * idx_in, cnt_in and e_atom are then unused (may be NULL), any row_cap is
+ * accepted, and E in ev is 0.
  * ws as for md_forces_lj. */
 int md_forces_mlp(const md_box_t *box, int64_t n, const uint32_t *xs,
                   int32_t row_cap, const int32_t *idx, const int32_t *count,
                   const md_mlp_t *mlp, const uint16_t *w, float *dEdG,
-                  float *e_atom, float *f, double *ev, int32_t flags,
-                  void *ws, size_t ws_bytes, void *stream);
+                  int32_t *idx_in, int32_t *cnt_in, float *e_atom, float *f,
+                  double *ev, int32_t flags, void *ws, size_t ws_bytes,
+                  void *stream);
 
 /* Host only.  Bytes of training workspace for batches of up to `batch`
  * atoms (md_mlp_moments, md_mlp_grad, md_mlp_train_step). */
@@ -377,6 +390,7 @@ typedef struct md_system {
     md_mlp_t mlp;               /* MD_POT_MLP */
     const uint16_t *mlp_w;      /* MD_POT_MLP: MD_MLP_NPARAM bfloat16 parameters */
     float *dEdG;                /* MD_POT_MLP: [16n] scratch */
+    int32_t *idx_in, *cnt_in;   /* MD_POT_MLP: compact list scratch, sized as idx, count */
 } md_system_t;
 
 /* Runs `steps` velocity-Verlet steps (Sec. 3.3) of the path: kick + drift

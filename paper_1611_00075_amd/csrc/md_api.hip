@@ -251,7 +251,8 @@ int md_mlp_descriptors(const md_box_t *box, int64_t n, const uint32_t *xs, int32
                        const int32_t *count, const md_mlp_t *mlp, float *G, void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
-    if (!mlp_ok(mlp) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8) return MD_ERR_ARG;
+    if (!mlp_ok(mlp) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8 || row_cap > MD_MLP_MAX_ROW)
+        return MD_ERR_ARG;
     if (n > 0 && (!xs || !idx || !count || !G)) return MD_ERR_ARG;
     return mlp_descriptors(box, n, xs, row_cap, idx, count, mlp, G, as_stream(stream));
 }
@@ -265,18 +266,21 @@ int md_mlp_eval(int64_t n, const float *G, const md_mlp_t *mlp, const uint16_t *
 }
 
 int md_forces_mlp(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t row_cap, const int32_t *idx,
-                  const int32_t *count, const md_mlp_t *mlp, const uint16_t *w, float *dEdG, float *e_atom, float *f,
-                  double *ev, int32_t flags, void *ws, size_t ws_bytes, void *stream)
+                  const int32_t *count, const md_mlp_t *mlp, const uint16_t *w, float *dEdG, int32_t *idx_in,
+                  int32_t *cnt_in, float *e_atom, float *f, double *ev, int32_t flags, void *ws, size_t ws_bytes,
+                  void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
     if (!mlp_ok(mlp) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8) return MD_ERR_ARG;
     if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE | MD_MLP_REUSE)) return MD_ERR_ARG;
+    const bool reuse = flags & MD_MLP_REUSE;
+    if (!reuse && row_cap > MD_MLP_MAX_ROW) return MD_ERR_ARG;
     if (n > 0 && (!xs || !idx || !count || !dEdG || !f)) return MD_ERR_ARG;
-    if (n > 0 && !(flags & MD_MLP_REUSE) && !w) return MD_ERR_ARG;
+    if (n > 0 && !reuse && (!w || !idx_in || !cnt_in)) return MD_ERR_ARG;
     if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
     WsLayout wl;
     if (int rc = ws_check_n(n, ws, ws_bytes, wl)) return rc;
-    return forces_mlp(box, n, xs, row_cap, idx, count, mlp, w, dEdG, e_atom, f, ev, flags, ws, wl,
+    return forces_mlp(box, n, xs, row_cap, idx, count, mlp, w, dEdG, idx_in, cnt_in, e_atom, f, ev, flags, ws, wl,
                       as_stream(stream));
 }
 
@@ -352,7 +356,8 @@ int md_run(md_system_t *sys, int64_t steps, void *stream)
             return MD_ERR_ARG;
         if (!f64 && !sys->xs) return MD_ERR_ARG;
         if (sys->potential == MD_POT_EAM && (!sys->rho || !sys->fprime)) return MD_ERR_ARG;
-        if (sys->potential == MD_POT_MLP && (!sys->mlp_w || !sys->dEdG)) return MD_ERR_ARG;
+        if (sys->potential == MD_POT_MLP && (!sys->mlp_w || !sys->dEdG || !sys->idx_in || !sys->cnt_in))
+            return MD_ERR_ARG;
     }
     WsLayout w;
     if (int rc = ws_check(&sys->grid, sys->n, sys->ws, sys->ws_bytes, w)) return rc;

@@ -144,8 +144,8 @@ int mlp_descriptors(const md_box_t *, int64_t, const uint32_t *, int32_t, const 
                     const md_mlp_t *, float *, hipStream_t);
 int mlp_eval(int64_t, const float *, const md_mlp_t *, const uint16_t *, float *, float *, hipStream_t);
 int forces_mlp(const md_box_t *, int64_t, const uint32_t *, int32_t, const int32_t *, const int32_t *,
-               const md_mlp_t *, const uint16_t *, float *, float *, float *, double *, int32_t, void *,
-               const WsLayout &, hipStream_t);
+               const md_mlp_t *, const uint16_t *, float *, int32_t *, int32_t *, float *, float *, double *, int32_t,
+               void *, const WsLayout &, hipStream_t);
 size_t mlp_workspace_bytes(int64_t batch);
 int mlp_moments(int64_t, const float *, double *, void *, hipStream_t);
 // gradient of the batch loss (grad, loss may be NULL); with adam, an Adam

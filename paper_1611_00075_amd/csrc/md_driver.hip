@@ -90,8 +90,8 @@ int forces(md_system_t *sys, const WsLayout &w, hipStream_t s)
                          nullptr, sys->flags & (MD_PAIR_FP64 | MD_NO_COMPENSATE), sys->ws, w, s);
     if (sys->potential == MD_POT_MLP)
         return forces_mlp(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->mlp, sys->mlp_w,
-                          sys->dEdG, nullptr, static_cast<float *>(sys->f), nullptr, sys->flags & MD_NO_COMPENSATE,
-                          sys->ws, w, s);
+                          sys->dEdG, sys->idx_in, sys->cnt_in, nullptr, static_cast<float *>(sys->f), nullptr,
+                          sys->flags & MD_NO_COMPENSATE, sys->ws, w, s);
     return forces_eam(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->fs, sys->rho,
                       sys->fprime, static_cast<float *>(sys->f), nullptr, nullptr, sys->flags & MD_NO_COMPENSATE,
                       sys->ws, w, s);

@@ -45,30 +45,39 @@ __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restr
     const int64_t i = sl.i;
     const int sub = sl.sub;
 
+    const SliceBufs b = slice_bufs(xs, n, idx, cap, blk);
     float fx = 0.f, fy = 0.f, fz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     double e = 0.0, np = 0.0, w[6] = {0, 0, 0, 0, 0, 0};
     if (i < n) {
         const uint4 pi = xs[i];
         const int32_t cnt = min(count[i], cap);
-        walk_row<TPA, U>(xs, ell_row(idx, i, cap), cnt, sub, [&](const uint4 &pj, bool valid) {
-            float dx, dy, dz;
-            disp<CUBIC>(pi, pj, p.ax, p.ay, p.az, dx, dy, dz);
-            const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-            const bool in = valid && r2 < p.rc2;
-            const float ir2 = __builtin_amdgcn_rcpf(r2);
-            const float s2 = p.sig2 * ir2;
-            const float s6 = s2 * s2 * s2;
-            float fs = p.eps24 * s6 * __builtin_fmaf(2.f, s6, -1.f) * ir2;
-            fs = in ? fs : 0.f;
-            acc_add<COMP>(fx, cx, fs, dx);
-            acc_add<COMP>(fy, cy, fs, dy);
-            acc_add<COMP>(fz, cz, fs, dz);
-            if (ENERGY && in) {
-                e += double(p.eps4 * (s6 * s6 - s6));
-                np += 1.0;
-                w[0] += double(fs * dx * dx); w[1] += double(fs * dy * dy); w[2] += double(fs * dz * dz);
-                w[3] += double(fs * dx * dy); w[4] += double(fs * dx * dz); w[5] += double(fs * dy * dz);
+        walk_buf<U, 3>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t) {
+            // the U pair forces are summed plainly, the sum is added compensated
+            float bx = 0.f, by = 0.f, bz = 0.f;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                float dx, dy, dz;
+                disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
+                const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+                const bool in = t + u * TPA < cnt && r2 < p.rc2;
+                const float ir2 = __builtin_amdgcn_rcpf(r2);
+                const float s2 = p.sig2 * ir2;
+                const float s6 = s2 * s2 * s2;
+                float fs = p.eps24 * s6 * __builtin_fmaf(2.f, s6, -1.f) * ir2;
+                fs = in ? fs : 0.f;
+                bx = __builtin_fmaf(fs, dx, bx);
+                by = __builtin_fmaf(fs, dy, by);
+                bz = __builtin_fmaf(fs, dz, bz);
+                if (ENERGY && in) {
+                    e += double(p.eps4 * (s6 * s6 - s6));
+                    np += 1.0;
+                    w[0] += double(fs * dx * dx); w[1] += double(fs * dy * dy); w[2] += double(fs * dz * dz);
+                    w[3] += double(fs * dx * dy); w[4] += double(fs * dx * dz); w[5] += double(fs * dy * dz);
+                }
             }
+            acc_sum<COMP>(fx, cx, bx);
+            acc_sum<COMP>(fy, cy, by);
+            acc_sum<COMP>(fz, cz, bz);
         });
     }
     const double gx = combine(fx, cx), gy = combine(fy, cy), gz = combine(fz, cz);
@@ -192,17 +201,23 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
     const int64_t i = sl.i;
     const int sub = sl.sub;
 
+    const SliceBufs b = slice_bufs(xs, n, idx, cap, blk);
     float s = 0.f, c = 0.f;
     if (i < n) {
         const uint4 pi = xs[i];
         const int32_t cnt = min(count[i], cap);
-        walk_row<TPA, U>(xs, ell_row(idx, i, cap), cnt, sub, [&](const uint4 &pj, bool valid) {
-            float dx, dy, dz;
-            disp<CUBIC>(pi, pj, p.ax, p.ay, p.az, dx, dy, dz);
-            const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-            float t = __builtin_amdgcn_sqrtf(r2) * p.len - p.d;
-            t = (valid && r2 < p.d2u) ? t : 0.f;
-            acc_add<COMP>(s, c, t, t);
+        walk_buf<U, 3>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
+            float bs = 0.f;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                float dx, dy, dz;
+                disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
+                const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+                float t = __builtin_amdgcn_sqrtf(r2) * p.len - p.d;
+                t = (t0 + u * TPA < cnt && r2 < p.d2u) ? t : 0.f;
+                bs = __builtin_fmaf(t, t, bs);
+            }
+            acc_sum<COMP>(s, c, bs);
         });
     }
     const double g = combine(s, c);
@@ -245,34 +260,44 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
     const int64_t i = sl.i;
     const int sub = sl.sub;
 
+    const SliceBufs b = slice_bufs(xs, n, idx, cap, blk);
     float fx = 0.f, fy = 0.f, fz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     double e = 0.0, w[6] = {0, 0, 0, 0, 0, 0};
     if (i < n) {
         const uint4 pi = xs[i];
         const float fpi = __uint_as_float(pi.w);
         const int32_t cnt = min(count[i], cap);
-        walk_row<TPA, U>(xs, ell_row(idx, i, cap), cnt, sub, [&](const uint4 &pj, bool valid) {
-            float dx, dy, dz;
-            disp<CUBIC>(pi, pj, p.ax, p.ay, p.az, dx, dy, dz);
-            const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-            const bool in_d = valid && r2 < p.d2u, in_c = valid && r2 < p.c2u;
-            const float ru = __builtin_amdgcn_sqrtf(r2);
-            const float r = ru * p.len;
-            const float dpsi = in_d ? (fpi + __uint_as_float(pj.w)) * 2.f * (r - p.d) : 0.f;
-            const float t = r - p.c;
-            const float poly = __builtin_fmaf(__builtin_fmaf(p.p2, t, p.p1), t, p.p0);
-            const float dpoly = __builtin_fmaf(2.f * p.p2, t, p.p1);
-            const float dV = in_c ? t * __builtin_fmaf(t, dpoly, 2.f * poly) : 0.f;
-            // -(dU/dr) / r in the displacement unit: F = g * (dx, dy, dz)
-            const float g = -(dpsi + dV) * __builtin_amdgcn_rcpf(ru);
-            acc_add<COMP>(fx, cx, g, dx);
-            acc_add<COMP>(fy, cy, g, dy);
-            acc_add<COMP>(fz, cz, g, dz);
-            if (ENERGY && (in_d || in_c)) {
-                if (in_c) e += double(t * t * poly);
-                w[0] += double(g * dx * dx); w[1] += double(g * dy * dy); w[2] += double(g * dz * dz);
-                w[3] += double(g * dx * dy); w[4] += double(g * dx * dz); w[5] += double(g * dy * dz);
+        walk_buf<U, 4>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
+            float bx = 0.f, by = 0.f, bz = 0.f;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                float dx, dy, dz;
+                disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
+                const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+                const bool valid = t0 + u * TPA < cnt;
+                const bool in_d = valid && r2 < p.d2u, in_c = valid && r2 < p.c2u;
+                const float ru = __builtin_amdgcn_sqrtf(r2);
+                const float r = ru * p.len;
+                const float dpsi = in_d ? (fpi + __uint_as_float(pj[u].w)) * 2.f * (r - p.d) : 0.f;
+                const float t = r - p.c;
+                const float poly = __builtin_fmaf(__builtin_fmaf(p.p2, t, p.p1), t, p.p0);
+                const float dpoly = __builtin_fmaf(2.f * p.p2, t, p.p1);
+                const float dV = in_c ? t * __builtin_fmaf(t, dpoly, 2.f * poly) : 0.f;
+                // -(dU/dr) / r in the displacement unit: F = g * (dx, dy, dz)
+                float g = -(dpsi + dV) * __builtin_amdgcn_rcpf(ru);
+                g = in_d || in_c ? g : 0.f;
+                bx = __builtin_fmaf(g, dx, bx);
+                by = __builtin_fmaf(g, dy, by);
+                bz = __builtin_fmaf(g, dz, bz);
+                if (ENERGY && (in_d || in_c)) {
+                    if (in_c) e += double(t * t * poly);
+                    w[0] += double(g * dx * dx); w[1] += double(g * dy * dy); w[2] += double(g * dz * dz);
+                    w[3] += double(g * dx * dy); w[4] += double(g * dx * dz); w[5] += double(g * dy * dz);
+                }
             }
+            acc_sum<COMP>(fx, cx, bx);
+            acc_sum<COMP>(fy, cy, by);
+            acc_sum<COMP>(fz, cz, bz);
         });
     }
     const double gx = combine(fx, cx), gy = combine(fy, cy), gz = combine(fz, cz);

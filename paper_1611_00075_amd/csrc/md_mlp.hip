@@ -1,11 +1,12 @@
 // Steps a8/a9: the learned descriptor-MLP potential (model in md.h).
 //
 // Forces, two passes (the shape of the embedded-atom kernels):
-//   pass 1 (k_mlp_atoms, kDescNet): per atom, the 16 radial descriptors over
-//     its list row (8 lanes per atom, as in the pair kernels); then, per
-//     tile of 16 atoms, the network and its backward pass to dE_i/dG_i on
-//     the BF16 matrix cores; dE_i/dG_i is stored (16 floats per atom);
-//   pass 2 (k_mlp_force): per pair within rc,
+//   pass 1a (k_mlp_desc): per atom, the 16 radial descriptors over its list
+//     row (8 lanes per atom, as in the pair kernels), evaluated only for
+//     the pairs within rc, which are also written out as a compact list;
+//   pass 1b (k_mlp_net): per tile of 16 atoms, the network and its backward
+//     pass to dE_i/dG_i on the BF16 matrix cores (dE_i/dG_i overwrites G_i);
+//   pass 2 (k_mlp_force): per pair of the compact list,
 //     s_ij = sum_k (dE_i/dG_ik + dE_j/dG_jk) g_k'(r), F_i -= s_ij R / r.
 // Training: k_mlp_grad (forward, loss, backward, weight gradients as
 // matrix-core products over atoms, one partial row per wavefront) and
@@ -208,11 +209,18 @@ __device__ __forceinline__ bf16x8 op(const WeightsLds &L, int o, int lane)
 // ---- the network on one tile of 16 atoms (one wavefront) --------------------
 
 struct Fwd {
-    f32x4 a1[4], a2[4];     // pre-activations of lane's atom, features 16t + 4g + r
-    f32x4 h[4];             // silu(a1) before rounding
+    f32x4 ds1[4], ds2[4];   // silu'(a1), silu'(a2) of lane's atom, features 16t + 4g + r
+    f32x4 h[4], h2[4];      // silu(a1) before rounding, silu(a2)
     bf16x8 h1[2];           // layer-2 B operand
     float E;                // energy of atom lane % 16
 };
+
+// silu(a) = a s and silu'(a) = s (1 + a (1 - s)), s = 1 / (1 + exp(-a))
+__device__ __forceinline__ float2 silu2(float a)
+{
+    const float s = sigm(a);
+    return make_float2(a * s, s * __builtin_fmaf(a, 1.f - s, 1.f));
+}
 
 __device__ __forceinline__ void forward(const WeightsLds &L, int lane, const bf16x8 &X, Fwd &F)
 {
@@ -220,37 +228,33 @@ __device__ __forceinline__ void forward(const WeightsLds &L, int lane, const bf1
     const f32x4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        F.a1[t] = mfma(op(L, kOpL1 + t, lane), X, z);
+        const f32x4 a = mfma(op(L, kOpL1 + t, lane), X, z);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) F.a1[t][r] += L.b1[16 * t + 4 * g + r];
+        for (int r = 0; r < 4; ++r) {
+            const float2 v = silu2(a[r] + L.b1[16 * t + 4 * g + r]);
+            F.h[t][r] = v.x;
+            F.ds1[t][r] = v.y;
+        }
     }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) F.h[t][r] = F.a1[t][r] * sigm(F.a1[t][r]);
     F.h1[0] = pack(F.h[0], F.h[1]);
     F.h1[1] = pack(F.h[2], F.h[3]);
     float e = 0.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        F.a2[t] = mfma(op(L, kOpL2 + 2 * t, lane), F.h1[0], z);
-        F.a2[t] = mfma(op(L, kOpL2 + 2 * t + 1, lane), F.h1[1], F.a2[t]);
+        f32x4 a = mfma(op(L, kOpL2 + 2 * t, lane), F.h1[0], z);
+        a = mfma(op(L, kOpL2 + 2 * t + 1, lane), F.h1[1], a);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int f = 16 * t + 4 * g + r;
-            F.a2[t][r] += L.b2[f];
-            e = __builtin_fmaf(L.w3[f], F.a2[t][r] * sigm(F.a2[t][r]), e);
+            const float2 v = silu2(a[r] + L.b2[f]);
+            F.h2[t][r] = v.x;
+            F.ds2[t][r] = v.y;
+            e = __builtin_fmaf(L.w3[f], F.h2[t][r], e);
         }
     }
     e += __shfl_xor(e, 16, kWave);
     e += __shfl_xor(e, 32, kWave);
     F.E = e + L.b3;
-}
-
-__device__ __forceinline__ float dsilu(float a)
-{
-    const float s = sigm(a);
-    return s * __builtin_fmaf(a, 1.f - s, 1.f);
 }
 
 // dE/dx for the tile: lane's atom, input features 4g + r
@@ -262,14 +266,14 @@ __device__ __forceinline__ f32x4 backward_input(const WeightsLds &L, int lane, c
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) d[t][r] = L.w3[16 * t + 4 * g + r] * dsilu(F.a2[t][r]);
+        for (int r = 0; r < 4; ++r) d[t][r] = L.w3[16 * t + 4 * g + r] * F.ds2[t][r];
     const bf16x8 D2[2] = {pack(d[0], d[1]), pack(d[2], d[3])};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         f32x4 p = mfma(op(L, kOpB2 + 2 * t, lane), D2[0], z);
         p = mfma(op(L, kOpB2 + 2 * t + 1, lane), D2[1], p);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) d[t][r] = p[r] * dsilu(F.a1[t][r]);
+        for (int r = 0; r < 4; ++r) d[t][r] = p[r] * F.ds1[t][r];
     }
     const bf16x8 D1[2] = {pack(d[0], d[1]), pack(d[2], d[3])};
     f32x4 dx = mfma(op(L, kOpB1, lane), D1[0], z);
@@ -278,30 +282,54 @@ __device__ __forceinline__ f32x4 backward_input(const WeightsLds &L, int lane, c
 
 // ---- pass 1 / descriptors / network ---------------------------------------
 
-enum AtomMode { kDesc = 0, kNet = 1, kDescNet = 2 };
-
-// Descriptor sums of atom i over the lanes `sub` of its row (unreduced).
+// Descriptor sums of one atom (unreduced over its 8 lanes), in two phases.
+// (1) The 8 lanes sweep the row; the distances of the pairs within rc are
+// packed into the atom's LDS segment `seg` and, if orow is not NULL, their
+// indices into the atom's compact row (the list pass 2 walks).  (2) The
+// Gaussians of the packed pairs, 8 at a time, so no lane computes a pair
+// beyond rc.  Returns the number of pairs within rc (in all 8 lanes).  All
+// lanes of the wave call it (cnt = 0 for atoms past the end).
 template <int U>
-__device__ __forceinline__ void descriptor(const MlpArgs &p, const uint4 *__restrict__ xs,
-                                           const int32_t *__restrict__ idx, const int32_t *__restrict__ count,
-                                           int32_t cap, int64_t i, int sub, float (&G)[kIn])
+__device__ __forceinline__ int32_t descriptor(const MlpArgs &p, const uint4 *__restrict__ xs,
+                                              const int32_t *__restrict__ row, int32_t cnt, const uint4 &pi,
+                                              int sub, int lane, float *seg, int32_t *__restrict__ orow,
+                                              float (&G)[kIn])
 {
-    const uint4 pi = xs[i];
-    const int32_t cnt = min(count[i], cap);
-    walk_row<kSlice, U>(xs, ell_row(idx, i, cap), cnt, sub, [&](const uint4 &pj, bool valid) {
-        float dx, dy, dz;
-        disp<false>(pi, pj, p.ax, p.ay, p.az, dx, dy, dz);
-        const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-        const bool in = valid && r2 < p.rc2;
-        const float r = __builtin_amdgcn_sqrtf(r2);
+    int32_t base = 0;
+    for (int32_t t0 = 0; t0 < cnt; t0 += U * kSlice) {
+        int32_t j[U];
+        uint4 pj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = row[ell_pos(min(t0 + u * kSlice + sub, cnt - 1))];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pj[u] = xs[j[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float dx, dy, dz;
+            disp<false>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
+            const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+            const bool in = t0 + u * kSlice + sub < cnt && r2 < p.rc2;
+            const uint32_t gm = uint32_t(__ballot(in) >> (lane & ~(kSlice - 1))) & 0xffu;
+            const int32_t pos = base + __popc(gm & ((1u << sub) - 1u));
+            if (in) {
+                seg[pos] = __builtin_amdgcn_sqrtf(r2);
+                if (orow) orow[ell_pos(pos)] = j[u];
+            }
+            base += __popc(gm);
+        }
+    }
+    wave_sync();
+    for (int32_t q = sub; q < base; q += kSlice) {
+        const float r = seg[q];
         float e[kIn];
         gaussians(p, r - p.c8, e);
         const float ph = p.phi * r;
         const float c = cos_z(ph * ph);
-        const float fc = in ? c * c : 0.f;
+        const float fc = c * c;
 #pragma unroll
         for (int k = 0; k < kIn; ++k) G[k] = __builtin_fmaf(e[k], fc, G[k]);
-    });
+    }
+    return base;
 }
 
 // Sum over the 8 lanes of an atom, scattered: lane `sub` ends with the totals
@@ -327,19 +355,46 @@ __device__ __forceinline__ void reduce_scatter8(float (&G)[kIn], int sub, float 
     }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_mlp_atoms(int64_t n, MlpArgs p, const uint4 *__restrict__ xs,
-                                                      int32_t cap, const int32_t *__restrict__ idx,
-                                                      const int32_t *__restrict__ count,
-                                                      const float *__restrict__ Gin, const uint16_t *__restrict__ w,
-                                                      float *__restrict__ Gout, float *__restrict__ e_atom,
-                                                      float *__restrict__ dEdG, double *__restrict__ part)
+// Pass 1a: raw descriptors G[n][16] of one slice of 8 atoms per wavefront
+// (8 lanes per atom) and, if idx_in is not NULL, the compact list of the
+// pairs within rc.  Dynamic LDS: cap floats per atom of the block.
+__global__ __launch_bounds__(kBlock) void k_mlp_desc(int64_t n, MlpArgs p, const uint4 *__restrict__ xs, int32_t cap,
+                                                     const int32_t *__restrict__ idx,
+                                                     const int32_t *__restrict__ count, float *__restrict__ G,
+                                                     int32_t *__restrict__ idx_in, int32_t *__restrict__ cnt_in)
 {
-    constexpr bool NET = MODE != kDesc;
+    extern __shared__ float seg_lds[];
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const SliceLane sl = slice_lane(blk);
+    const int64_t i = sl.i;
+    const int sub = sl.sub, lane = threadIdx.x % kWave;
+    float g[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) g[k] = 0.f;
+    const bool live = i < n;
+    const int32_t cnt = live ? min(count[i], cap) : 0;
+    const uint4 pi = live ? xs[i] : make_uint4(0, 0, 0, 0);
+    float *seg = seg_lds + (threadIdx.x / kSlice) * cap;
+    const int32_t nin = descriptor<2>(p, xs, live ? ell_row(idx, i, cap) : idx, cnt, pi, sub, lane, seg,
+                                      idx_in && live ? idx_in + (ell_row(idx_in, i, cap) - idx_in) : nullptr, g);
+    if (cnt_in && live && sub == 0) cnt_in[i] = nin;
+    float v0, v1;
+    reduce_scatter8(g, sub, v0, v1);
+    if (live) *reinterpret_cast<float2 *>(G + i * kIn + 2 * sub) = make_float2(v0, v1);
+}
+
+// Pass 1b: the network on raw descriptors, tiles of 16 atoms per wavefront,
+// persistent blocks (the weight operands are staged once per block).
+// Energies E_i (e_atom, may be NULL; FP64 block partial in part if not NULL)
+// and dE/dG (dEdG, may be NULL).  Gin and dEdG may be the same buffer: a
+// wavefront reads its 16 rows before it writes them.
+__global__ __launch_bounds__(kBlock) void k_mlp_net(int64_t n, MlpArgs p, const float *Gin,
+                                                    const uint16_t *__restrict__ w, float *__restrict__ e_atom,
+                                                    float *dEdG, double *__restrict__ part)
+{
     __shared__ WeightsLds L;
-    __shared__ uint32_t xt[kBlock / kWave][kTile][kIn / 2];   // normalised descriptors, bf16 pairs
     __shared__ double red[kBlock / kWave];
-    if (NET) stage_weights(L, w, p);
+    stage_weights(L, w, p);
 
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -349,65 +404,36 @@ __global__ __launch_bounds__(kBlock) void k_mlp_atoms(int64_t n, MlpArgs p, cons
     double esum = 0.0;
 
     for (int64_t c = c0; c < c1; ++c) {
-        const int64_t i0 = c * kChunk + int64_t(wave) * kTile;
+        const int64_t i = c * kChunk + int64_t(wave) * kTile + m;
         bf16x8 X = {};
-        if (MODE != kNet) {
-#pragma unroll 1
-            for (int h = 0; h < 2; ++h) {
-                const int64_t i = i0 + 8 * h + lane / kSlice;
-                const int sub = lane % kSlice;
-                float G[kIn];
+        if (g < 2 && i < n) {
+            const float4 u0 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g);
+            const float4 u1 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g + 4);
+            const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+            float u[8];
 #pragma unroll
-                for (int k = 0; k < kIn; ++k) G[k] = 0.f;
-                if (i < n) descriptor<2>(p, xs, idx, count, cap, i, sub, G);
-                float v0, v1;
-                reduce_scatter8(G, sub, v0, v1);
-                if (MODE == kDesc) {
-                    if (i < n) *reinterpret_cast<float2 *>(Gout + i * kIn + 2 * sub) = make_float2(v0, v1);
-                } else {
-                    const float x0 = (v0 - L.mean[2 * sub]) * L.inv_std[2 * sub];
-                    const float x1 = (v1 - L.mean[2 * sub + 1]) * L.inv_std[2 * sub + 1];
-                    xt[wave][8 * h + lane / kSlice][sub] = uint32_t(f_to_bf16(x0)) | (uint32_t(f_to_bf16(x1)) << 16);
-                }
-            }
-            if (!NET) continue;
-            wave_sync();
-            if (g < 2) X = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&xt[wave][m][4 * g]));
-            wave_sync();
-        } else {
-            const int64_t i = i0 + m;
-            if (g < 2 && i < n) {
-                const float4 u0 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g);
-                const float4 u1 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g + 4);
-                const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-                float u[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) u[j] = (v[j] - L.mean[8 * g + j]) * L.inv_std[8 * g + j];
-                X = pack8(u);
-            }
+            for (int j = 0; j < 8; ++j) u[j] = (v[j] - L.mean[8 * g + j]) * L.inv_std[8 * g + j];
+            X = pack8(u);
         }
-        if (NET) {
-            Fwd F;
-            forward(L, lane, X, F);
-            const int64_t i = i0 + m;
-            if (g == 0 && i < n) {
-                if (e_atom) e_atom[i] = F.E;
-                esum += double(F.E);
-            }
-            if (dEdG) {
-                const f32x4 dx = backward_input(L, lane, F);
-                if (i < n) {
-                    float4 o;
-                    o.x = dx[0] * L.inv_std[4 * g + 0];
-                    o.y = dx[1] * L.inv_std[4 * g + 1];
-                    o.z = dx[2] * L.inv_std[4 * g + 2];
-                    o.w = dx[3] * L.inv_std[4 * g + 3];
-                    *reinterpret_cast<float4 *>(dEdG + i * kIn + 4 * g) = o;
-                }
+        Fwd F;
+        forward(L, lane, X, F);
+        if (g == 0 && i < n) {
+            if (e_atom) e_atom[i] = F.E;
+            esum += double(F.E);
+        }
+        if (dEdG) {
+            const f32x4 dx = backward_input(L, lane, F);
+            if (i < n) {
+                float4 o;
+                o.x = dx[0] * L.inv_std[4 * g + 0];
+                o.y = dx[1] * L.inv_std[4 * g + 1];
+                o.z = dx[2] * L.inv_std[4 * g + 2];
+                o.w = dx[3] * L.inv_std[4 * g + 3];
+                *reinterpret_cast<float4 *>(dEdG + i * kIn + 4 * g) = o;
             }
         }
     }
-    if (NET && part) {
+    if (part) {
         double v[1] = {esum};
         block_sum<1>(v, red);
         if (threadIdx.x == 0) {
@@ -588,9 +614,8 @@ __global__ __launch_bounds__(kBlock) void k_mlp_grad(int64_t batch, const int32_
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int f = 16 * t + 4 * g + r;
-                    const float a2 = F.a2[t][r], s2 = sigm(a2);
-                    gw3[4 * t + r] = __builtin_fmaf(gE, a2 * s2, gw3[4 * t + r]);
-                    d[t][r] = gE * L.w3[f] * (s2 * __builtin_fmaf(a2, 1.f - s2, 1.f));
+                    gw3[4 * t + r] = __builtin_fmaf(gE, F.h2[t][r], gw3[4 * t + r]);
+                    d[t][r] = gE * L.w3[f] * F.ds2[t][r];
                     gb2[4 * t + r] += d[t][r];
                     T.d2T[f][h * kTile + m] = f_to_bf16(d[t][r]);
                     T.h1T[f][h * kTile + m] = f_to_bf16(F.h[t][r]);
@@ -602,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_grad(int64_t batch, const int32_
                 pr = mfma(op(L, kOpB2 + 2 * t + 1, lane), D2[1], pr);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float d1 = pr[r] * dsilu(F.a1[t][r]);
+                    const float d1 = pr[r] * F.ds1[t][r];
                     gb1[4 * t + r] += d1;
                     T.d1T[16 * t + 4 * g + r][h * kTile + m] = f_to_bf16(d1);
                 }
@@ -729,6 +754,10 @@ __global__ void k_mlp_moments_final(int64_t n, int32_t blocks, const double *__r
     out[kIn + k] = var > 0.0 ? sqrt(var) : 0.0;
 }
 
+size_t seg_bytes(int32_t cap) { return size_t(kBlock / kSlice) * size_t(cap) * sizeof(float); }
+
+uint32_t slice_blocks(int64_t n) { return uint32_t((n * kSlice + kBlock - 1) / kBlock); }
+
 uint32_t atom_grid(int64_t n)
 {
     const int64_t chunks = (n + kChunk - 1) / kChunk;
@@ -770,9 +799,8 @@ int mlp_descriptors(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t 
 {
     if (n == 0) return MD_OK;
     const MlpArgs a = make_args(box, mlp);
-    hipLaunchKernelGGL(k_mlp_atoms<kDesc>, dim3(atom_grid(n)), dim3(kBlock), 0, s, n, a,
-                       reinterpret_cast<const uint4 *>(xs), cap, idx, count, nullptr, nullptr, G, nullptr, nullptr,
-                       nullptr);
+    hipLaunchKernelGGL(k_mlp_desc, dim3(slice_blocks(n)), dim3(kBlock), seg_bytes(cap), s, n, a,
+                       reinterpret_cast<const uint4 *>(xs), cap, idx, count, G, nullptr, nullptr);
     MD_HIP_TRY(hipGetLastError());
     return MD_OK;
 }
@@ -782,15 +810,15 @@ int mlp_eval(int64_t n, const float *G, const md_mlp_t *mlp, const uint16_t *w, 
 {
     if (n == 0) return MD_OK;
     const MlpArgs a = make_args(nullptr, mlp);
-    hipLaunchKernelGGL(k_mlp_atoms<kNet>, dim3(atom_grid(n)), dim3(kBlock), 0, s, n, a, nullptr, 0, nullptr, nullptr,
-                       G, w, nullptr, e_atom, dEdG, nullptr);
+    hipLaunchKernelGGL(k_mlp_net, dim3(atom_grid(n)), dim3(kBlock), 0, s, n, a, G, w, e_atom, dEdG, nullptr);
     MD_HIP_TRY(hipGetLastError());
     return MD_OK;
 }
 
 int forces_mlp(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t cap, const int32_t *idx,
-               const int32_t *count, const md_mlp_t *mlp, const uint16_t *w, float *dEdG, float *e_atom, float *f,
-               double *ev, int32_t flags, void *ws, const WsLayout &wl, hipStream_t s)
+               const int32_t *count, const md_mlp_t *mlp, const uint16_t *w, float *dEdG, int32_t *idx_in,
+               int32_t *cnt_in, float *e_atom, float *f, double *ev, int32_t flags, void *ws, const WsLayout &wl,
+               hipStream_t s)
 {
     const bool energy = flags & MD_ENERGY;
     const bool comp = !(flags & MD_NO_COMPENSATE);
@@ -798,26 +826,35 @@ int forces_mlp(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t cap, 
     double *part1 = ws_ptr<double>(ws, wl.red1);
     double *part2 = ws_ptr<double>(ws, wl.red2);
     const uint32_t g1 = n > 0 && !reuse ? atom_grid(n) : 0;
-    const uint32_t g2 = n > 0 ? uint32_t((n * kSlice + kBlock - 1) / kBlock) : 0;
+    const uint32_t g2 = n > 0 ? slice_blocks(n) : 0;
     if (int64_t(g1) > wl.red_blocks || int64_t(g2) > wl.red_blocks) return MD_ERR_WORKSPACE;
     const MlpArgs a = make_args(box, mlp);
     const uint4 *q = reinterpret_cast<const uint4 *>(xs);
     if (n > 0) {
-        if (!reuse)
-            hipLaunchKernelGGL(k_mlp_atoms<kDescNet>, dim3(g1), dim3(kBlock), 0, s, n, a, q, cap, idx, count, nullptr,
-                               w, nullptr, e_atom, dEdG, energy ? part1 : nullptr);
+        if (!reuse) {
+            // pass 1a: descriptors into the dEdG buffer and the compact list;
+            // pass 1b: the network overwrites each row with dE/dG in place
+            hipLaunchKernelGGL(k_mlp_desc, dim3(g2), dim3(kBlock), seg_bytes(cap), s, n, a, q, cap, idx, count,
+                               dEdG, idx_in, cnt_in);
+            hipLaunchKernelGGL(k_mlp_net, dim3(g1), dim3(kBlock), 0, s, n, a, dEdG, w, e_atom, dEdG,
+                               energy ? part1 : nullptr);
+        }
         const float4 *d4 = reinterpret_cast<const float4 *>(dEdG);
+        // pass 2 walks the compact list of pairs within rc (the full list when
+        // dE/dG is given)
+        const int32_t *pidx = reuse ? idx : idx_in;
+        const int32_t *pcnt = reuse ? count : cnt_in;
         if (energy && comp)
-            hipLaunchKernelGGL((k_mlp_force<2, true, true>), dim3(g2), dim3(kBlock), 0, s, n, a, q, cap, idx, count,
+            hipLaunchKernelGGL((k_mlp_force<2, true, true>), dim3(g2), dim3(kBlock), 0, s, n, a, q, cap, pidx, pcnt,
                                d4, f, part2);
         else if (energy)
-            hipLaunchKernelGGL((k_mlp_force<2, true, false>), dim3(g2), dim3(kBlock), 0, s, n, a, q, cap, idx, count,
+            hipLaunchKernelGGL((k_mlp_force<2, true, false>), dim3(g2), dim3(kBlock), 0, s, n, a, q, cap, pidx, pcnt,
                                d4, f, part2);
         else if (comp)
-            hipLaunchKernelGGL((k_mlp_force<2, false, true>), dim3(g2), dim3(kBlock), 0, s, n, a, q, cap, idx, count,
+            hipLaunchKernelGGL((k_mlp_force<2, false, true>), dim3(g2), dim3(kBlock), 0, s, n, a, q, cap, pidx, pcnt,
                                d4, f, part2);
         else
-            hipLaunchKernelGGL((k_mlp_force<2, false, false>), dim3(g2), dim3(kBlock), 0, s, n, a, q, cap, idx, count,
+            hipLaunchKernelGGL((k_mlp_force<2, false, false>), dim3(g2), dim3(kBlock), 0, s, n, a, q, cap, pidx, pcnt,
                                d4, f, part2);
         MD_HIP_TRY(hipGetLastError());
     }

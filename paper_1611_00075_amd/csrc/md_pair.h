@@ -65,6 +65,76 @@ __device__ __forceinline__ void walk_row(const uint4 *__restrict__ xs, const int
     }
 }
 
+// s += v with the running error of the sum compensated (Kahan).
+template <bool COMP>
+__device__ __forceinline__ void acc_sum(float &s, float &c, float v)
+{
+    if (COMP) {
+        const float y = v - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    } else {
+        s += v;
+    }
+}
+
+// Raw buffer resource over `bytes` bytes at `base` (gfx9 raw buffer
+// semantics: a load at a byte offset >= bytes returns zero, so no load
+// leaves the range).  base and bytes must be wave-uniform.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, int(bytes), 0x00020000);
+}
+
+// Row walk through buffer loads.  The wavefront holds one slice of 8 atoms
+// (lane = 8 * atom + sub); the slice's block of the list is one buffer
+// (row_r, cap * 32 bytes), in which entry sub + 8 q of the lane's atom sits
+// at byte q * 256 + 4 * lane: one lane offset plus an immediate per load.
+// Per iteration each lane reads U entries, then their U positions (xs_r,
+// 16 bytes per atom, WORDS = 3 or 4 words read), then calls
+// body(pj, t) with the U positions of entries t + 8 u.  Entries past the
+// row end are read from the row's tail or as zero past the block and must
+// be masked by the body (t + 8 u >= cnt); their position loads stay inside
+// the bounded xs buffer whatever index they hold.
+template <int U, int WORDS, typename Body>
+__device__ __forceinline__ void walk_buf(const __amdgpu_buffer_rsrc_t &xs_r, const __amdgpu_buffer_rsrc_t &row_r,
+                                         int32_t cnt, int sub, Body &&body)
+{
+    uint32_t off = (threadIdx.x % kWave) * 4u;
+    for (int32_t t = sub; t < cnt; t += U * kSlice, off += U * 256u) {
+        uint32_t j[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = __builtin_amdgcn_raw_buffer_load_b32(row_r, off + u * 256u, 0, 0);
+        uint4 pj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (WORDS == 4) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(xs_r, j[u] << 4, 0, 0);
+                pj[u] = make_uint4(v[0], v[1], v[2], v[3]);
+            } else {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b96(xs_r, j[u] << 4, 0, 0);
+                pj[u] = make_uint4(v[0], v[1], v[2], 0u);
+            }
+        }
+        body(pj, t);
+    }
+}
+
+// Buffers of a force kernel's wavefront: the positions (n < 2^28 atoms) and
+// its slice's block of the list.
+struct SliceBufs {
+    __amdgpu_buffer_rsrc_t xs, row;
+};
+
+__device__ __forceinline__ SliceBufs slice_bufs(const void *xs, int64_t n, const int32_t *idx, int32_t cap,
+                                                uint32_t blk)
+{
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int64_t slice = int64_t(blk) * (kBlock / kWave) + wave;
+    return {make_rsrc(xs, uint32_t(n) * 16u), make_rsrc(idx + slice * cap * kSlice, uint32_t(cap) * 32u)};
+}
+
 // The 8 lanes of one atom are consecutive: combine over them in FP64.
 __device__ __forceinline__ double combine(float s, float c)
 {

@@ -67,10 +67,12 @@ def rng_for(seed: int, purpose: str) -> np.random.Generator:
 
 def fcc_sites(nx: int, ny: int, nz: int, a: float) -> np.ndarray:
     """fcc sites in id order: id = 4*((ix*ny + iy)*nz + iz) + b."""
-    ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz),
-                             indexing="ij")
-    cells = np.stack([ix, iy, iz], axis=-1).reshape(-1, 1, 3).astype(np.float64)
-    return ((cells + FCC_BASIS[None]) * a).reshape(-1, 3)
+    out = np.empty((nx, ny, nz, 4, 3))
+    for b in range(4):
+        out[:, :, :, b, 0] = (np.arange(nx)[:, None, None] + FCC_BASIS[b, 0]) * a
+        out[:, :, :, b, 1] = (np.arange(ny)[None, :, None] + FCC_BASIS[b, 1]) * a
+        out[:, :, :, b, 2] = (np.arange(nz)[None, None, :] + FCC_BASIS[b, 2]) * a
+    return out.reshape(-1, 3)
 
 
 def fcc_lattice_constant(density: float) -> float:
@@ -171,10 +173,13 @@ def lj_slab_cluster(nxy: int = 251, nz_slab: int = 125, density: float = 0.8442,
     slab = fcc_sites(nxy, nxy, nz_slab, a)
     centre = np.array([0.5 * L, 0.5 * L, 0.5 * nz_slab * a])
     R = (3.0 * cluster_atoms / (4.0 * math.pi * cluster_density)) ** (1.0 / 3.0)
-    d = slab - centre
-    keep = np.sum(d * d, axis=1) >= (R + 0.5) ** 2
+    keep = np.ones(len(slab), dtype=bool)
+    step = 1 << 22
+    for k in range(0, len(slab), step):
+        d = slab[k:k + step] - centre
+        keep[k:k + step] = np.einsum("ij,ij->i", d, d) >= (R + 0.5) ** 2
     slab = slab[keep]
-    del d, keep
+    del keep
     a2 = fcc_lattice_constant(cluster_density)
     m = int(math.ceil(R / a2)) + 1
     cl = fcc_sites(2 * m, 2 * m, 2 * m, a2) - m * a2 + centre

@@ -76,7 +76,8 @@ class System(C.Structure):
                 ("row_cap_needed", C.c_int32), ("potential", C.c_int32), ("flags", C.c_int32),
                 ("need_build", C.c_int32), ("phase", C.c_int32), ("timing", C.c_int32), ("pad_", C.c_int32),
                 ("force_ms", C.c_double), ("force_calls", C.c_int64),
-                ("mlp", MLP), ("mlp_w", C.c_void_p), ("dEdG", C.c_void_p)]
+                ("mlp", MLP), ("mlp_w", C.c_void_p), ("dEdG", C.c_void_p), ("idx_in", C.c_void_p),
+                ("cnt_in", C.c_void_p)]
 
 
 MD_POT_LJ, MD_POT_EAM, MD_POT_MLP = 0, 1, 2
@@ -119,7 +120,7 @@ def lib():
                                          _vp, _vp]
         L.md_mlp_eval.argtypes = [C.c_int64, _vp, C.POINTER(MLP), _vp, _vp, _vp, _vp]
         L.md_forces_mlp.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(MLP), _vp,
-                                    _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+                                    _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
         L.md_mlp_workspace_bytes.argtypes = [C.c_int64]
         L.md_mlp_workspace_bytes.restype = C.c_size_t
         L.md_mlp_moments.argtypes = [C.c_int64, _vp, _vp, _vp, C.c_size_t, _vp]
@@ -288,14 +289,19 @@ def md_mlp_eval(n: int, G, mlp: MLP, w, e_atom, dEdG=None, stream=None):
                              _ptr(dEdG, torch.float32, MD_MLP_IN * n, "dEdG"), _stream(stream)), "md_mlp_eval")
 
 
-def md_forces_mlp(L, n: int, xs, row_cap: int, idx, count, mlp: MLP, w, dEdG, e_atom, f, ev, flags: int, ws,
-                  stream=None):
+MD_MLP_MAX_ROW = 256
+
+
+def md_forces_mlp(L, n: int, xs, row_cap: int, idx, count, mlp: MLP, w, dEdG, idx_in, cnt_in, e_atom, f, ev,
+                  flags: int, ws, stream=None):
     import torch
     _check(lib().md_forces_mlp(C.byref(box(L)), int(n), _ptr(xs, torch.int32, 4 * n, "xs"), int(row_cap),
                                _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"),
                                _ptr(count, torch.int32, n, "count"), C.byref(mlp),
                                _ptr(w, torch.int16, MD_MLP_NPARAM, "w"),
                                _ptr(dEdG, torch.float32, MD_MLP_IN * n, "dEdG"),
+                               _ptr(idx_in, torch.int32, ell_size(n, row_cap), "idx_in"),
+                               _ptr(cnt_in, torch.int32, n, "cnt_in"),
                                _ptr(e_atom, torch.float32, n, "e_atom"), _ptr(f, torch.float32, 3 * n, "f"),
                                _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
                                _stream(stream)), "md_forces_mlp")

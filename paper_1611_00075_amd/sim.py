@@ -87,7 +87,8 @@ class Simulation:
         self.max_count = torch.zeros(1, dtype=torch.int32, device=d)
         # row capacity: the expected neighbour count of a dense region plus slack
         self.row_cap = (int(row_cap) + 7) // 8 * 8 if row_cap else 64
-        self.idx = torch.empty(max(M.ell_size(n, self.row_cap), 1), dtype=torch.int32, device=d)
+        self.idx_in = self.cnt_in = None
+        self._alloc_lists()
         self.ws = torch.empty(M.md_workspace_bytes(self.grid, n), dtype=torch.uint8, device=d)
         M.md_workspace_init(self.grid, n, self.ws)
         self.status = torch.zeros(2, dtype=torch.int32, device=d)
@@ -106,6 +107,15 @@ class Simulation:
         self.events = None
         self.rebuild()
         self.compute_forces(energy=False)
+
+    def _alloc_lists(self):
+        """List buffers for the current row capacity (and, for the learned
+        potential, the compact-list scratch of the same size)."""
+        size = max(M.ell_size(self.n, self.row_cap), 1)
+        self.idx = torch.empty(size, dtype=torch.int32, device=self.dev)
+        if self.potential == "mlp":
+            self.idx_in = torch.empty(size, dtype=torch.int32, device=self.dev)
+            self.cnt_in = torch.zeros(max(self.n, 1), dtype=torch.int32, device=self.dev)
 
     # ------------------------------------------------------------------
     def rebuild(self):
@@ -126,7 +136,7 @@ class Simulation:
                                            self.count, self.max_count, self.ws)
         if rc == M.MD_ERR_CAPACITY:
             self.row_cap = (int(longest * self.list_slack) + 4 + 7) // 8 * 8
-            self.idx = torch.empty(max(M.ell_size(n, self.row_cap), 1), dtype=torch.int32, device=self.dev)
+            self._alloc_lists()
             rc, longest = M.md_build_neighbors(self.grid, n, self.x, self.cell_start, self.row_cap, self.idx,
                                                self.count, self.max_count, self.ws)
         self.longest = longest
@@ -150,7 +160,7 @@ class Simulation:
                             self.fprime, self.f, self.ev, fl, self.ws, e_atom=ea)
         else:
             M.md_forces_mlp(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.mlp, self.mlp_w,
-                            self.dEdG, ea, self.f, self.ev, fl, self.ws)
+                            self.dEdG, self.idx_in, self.cnt_in, ea, self.f, self.ev, fl, self.ws)
 
     def descriptors(self, spec, out=None):
         """Raw MLP descriptors (n, 16) of the current positions in the
@@ -228,6 +238,7 @@ class Simulation:
         S.potential = {"lj": M.MD_POT_LJ, "eam": M.MD_POT_EAM, "mlp": M.MD_POT_MLP}[self.potential]
         if self.potential == "mlp":
             S.mlp, S.mlp_w, S.dEdG = self.mlp, ptr(self.mlp_w), ptr(self.dEdG)
+            S.idx_in, S.cnt_in = ptr(self.idx_in), ptr(self.cnt_in)
         S.flags = self.flags
         return S
 
@@ -242,9 +253,10 @@ class Simulation:
             rc = M.md_run(S, target - S.step)
             if rc == M.MD_ERR_CAPACITY:
                 self.row_cap = (int(S.row_cap_needed * self.list_slack) + 4 + 7) // 8 * 8
-                self.idx = torch.empty(max(M.ell_size(self.n, self.row_cap), 1), dtype=torch.int32,
-                                       device=self.dev)
+                self._alloc_lists()
                 S.idx, S.row_cap = self.idx.data_ptr(), self.row_cap
+                if self.potential == "mlp":
+                    S.idx_in, S.cnt_in = self.idx_in.data_ptr(), self.cnt_in.data_ptr()
                 S.need_build = 1
         self.step_count, self.builds = S.step, S.builds
         return S.force_ms, S.force_calls

@@ -1,0 +1,167 @@
+"""Parity at the workloads' full sizes, in the configuration the benchmark
+times: the GPU path runs the whole system; the FP64 oracle recomputes the
+forces of sampled regions.
+
+A region is a cube of "core" atoms plus every atom within a buffer around
+it wide enough that the core atoms' forces depend on nothing outside (LJ:
+the cutoff; EAM and the learned potential: twice the cutoff, because the
+force on i depends on the densities or descriptors of its neighbours).  The
+region is cut out with the minimum image and placed in a box large enough
+that no periodic image comes within reach, so the oracle's forces on the
+core atoms are those of the full periodic system.
+
+Bars as in the small-system tests: FP32 LJ and EAM forces 1e-5 normwise
+over the sampled core atoms; the learned potential closer to the oracle's
+BF16 evaluation than half the whole BF16 rounding effect.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1611_00075_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1611_00075_amd import md
+    md.lib()
+    return md
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _regions(x, L, centres, core, buf, reach):
+    """Cut-outs around each centre: (positions in a vacuum box, box, core
+    mask, indices into x)."""
+    out = []
+    for c in centres:
+        d = x - c
+        d -= L * np.round(d / L)
+        sel = np.nonzero(np.all(np.abs(d) < core + buf, axis=1))[0]
+        half = core + buf
+        Lb = np.full(3, 4.0 * half + 2.0 * reach)
+        pos = d[sel] + 0.5 * Lb
+        out.append((pos, Lb, np.all(np.abs(d[sel]) < core, axis=1), sel))
+    return out
+
+
+def _centres(x, k, seed):
+    rng = np.random.default_rng(seed)
+    return x[rng.choice(len(x), k, replace=False)]
+
+
+def _check_fp32(fg, fo, what):
+    err = np.linalg.norm(fg - fo) / np.linalg.norm(fo)
+    _say(f"{what}: FP32 force error over sampled core atoms (normwise) {err:.2e}")
+    assert err < 1e-5, err
+
+
+def test_lj_voids_full_size(M, orc):
+    """The 1.23 M-atom void system after 20 driver steps (with rebuilds)."""
+    from paper_1611_00075_amd.sim import Simulation
+    s = inputs.lj_voids()
+    sim = Simulation(s.L, s.x, s.v, skin=0.3, dt=0.005)
+    sim.run(20)
+    x, fg = sim.positions(), sim.forces().astype(np.float64)
+    assert sim.builds >= 2
+    del sim
+    torch.cuda.empty_cache()
+    fo_all, fg_all = [], []
+    for pos, Lb, core, sel in _regions(x, s.L, _centres(x, 4, 1), 5.0, 2.8, 2.8):
+        off, idx = orc.neighbors_brute(pos, Lb, 2.8)
+        fo, _ = orc.forces_lj(pos, Lb, off, idx)
+        fo_all.append(fo[core])
+        fg_all.append(fg[sel[core]])
+    _check_fp32(np.concatenate(fg_all), np.concatenate(fo_all), "LJ voids 1.23M")
+
+
+def test_eam_full_size(M, orc):
+    """The 4 M-atom Cu crystal after 20 driver steps."""
+    from paper_1611_00075_amd import mlp as P
+    s = inputs.eam_cu()
+    sim = P.eam_simulation(s)
+    sim.run(20)
+    x, fg = sim.positions(), sim.forces().astype(np.float64)
+    del sim
+    torch.cuda.empty_cache()
+    fo_all, fg_all = [], []
+    for pos, Lb, core, sel in _regions(x, s.L, _centres(x, 3, 2), 8.0, 10.8, 5.4):
+        off, idx = orc.neighbors_brute(pos, Lb, 5.4)
+        fo = orc.forces_eam(pos, Lb, off, idx, inputs.FS_CU)["f"]
+        fo_all.append(fo[core])
+        fg_all.append(fg[sel[core]])
+    _check_fp32(np.concatenate(fg_all), np.concatenate(fo_all), "EAM Cu 4M")
+
+
+def test_mlp_full_size(M, orc):
+    """MLP forces of the 4 M-atom crystal (thermalised by 20 EAM steps),
+    random BF16 network."""
+    from oracle import mlp as om
+    from paper_1611_00075_amd import mlp as P
+    from paper_1611_00075_amd.sim import Simulation
+    s = inputs.eam_cu()
+    se = P.eam_simulation(s)
+    se.run(20)
+    x = se.positions()
+    del se
+    torch.cuda.empty_cache()
+    mean = np.linspace(0.2, 3.0, 16).astype(np.float32).astype(np.float64)
+    inv = np.linspace(2.0, 0.5, 16).astype(np.float32).astype(np.float64)
+    bits = P.bf16_bits(P.init_params(4, w3_scale=0.3))
+    p = P.bf16_values(bits)
+    sim = Simulation(s.L, x, np.zeros_like(x), potential="mlp", mlp=P.spec(mean, inv), mlp_w=bits.cuda(),
+                     skin=1.0, dt=1.0, mass=inputs.CU_MASS_AMU, force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
+    fg = sim.forces().astype(np.float64)
+    del sim
+    torch.cuda.empty_cache()
+    sp = om.Spec(mean=mean, inv_std=inv)
+    g16, g64, o16 = [], [], []
+    for pos, Lb, core, sel in _regions(x, s.L, _centres(x, 2, 3), 7.0, 11.0, 6.0):
+        off, idx = orc.neighbors_brute(pos, Lb, 6.0)
+        G = om.descriptors(pos, Lb, off, idx, sp)
+        f16, _ = om.forces(pos, Lb, off, idx, sp, om.energy(G, sp, p, bf16=True)[1])
+        f64, _ = om.forces(pos, Lb, off, idx, sp, om.energy(G, sp, p, bf16=False)[1])
+        o16.append(f16[core])
+        g64.append(f64[core])
+        g16.append(fg[sel[core]])
+    fgc, f16c, f64c = map(np.concatenate, (g16, o16, g64))
+    err, eff = np.linalg.norm(fgc - f16c), np.linalg.norm(f16c - f64c)
+    _say(f"MLP 4M: |gpu - bf16 oracle| {err / np.linalg.norm(f16c):.2e}, BF16 effect "
+         f"{eff / np.linalg.norm(f16c):.2e} (normwise, sampled core atoms)")
+    assert err < 0.5 * eff
+
+
+def test_slab_cluster_full_size(M, orc):
+    """The 32 M-atom slab with its dense cluster after 10 driver steps;
+    regions at the cluster's edge, the slab's free surface and the bulk."""
+    from paper_1611_00075_amd.sim import Simulation
+    _say("slab+cluster: generating 32 M atoms")
+    s = inputs.lj_slab_cluster()
+    _say(f"slab+cluster: {s.n} atoms on the GPU")
+    sim = Simulation(s.L, s.x, s.v, skin=0.3, dt=0.005)
+    sim.run(10)
+    x, fg = sim.positions(), sim.forces().astype(np.float64)
+    del sim
+    torch.cuda.empty_cache()
+    L = s.L
+    c = np.array([0.5 * L[0], 0.5 * L[1], 0.5 * 125 * s.meta["a"]])
+    R = s.meta["R"]
+    centres = [c + np.array([R, 0.0, 0.0]),                      # cluster / slab interface
+               np.array([0.3 * L[0], 0.7 * L[1], 125 * s.meta["a"]]),   # free surface
+               np.array([0.1 * L[0], 0.2 * L[1], 0.25 * 125 * s.meta["a"]])]  # bulk
+    fo_all, fg_all = [], []
+    for pos, Lb, core, sel in _regions(x, L, centres, 5.0, 2.8, 2.8):
+        off, idx = orc.neighbors_brute(pos, Lb, 2.8)
+        fo, _ = orc.forces_lj(pos, Lb, off, idx)
+        fo_all.append(fo[core])
+        fg_all.append(fg[sel[core]])
+    _check_fp32(np.concatenate(fg_all), np.concatenate(fo_all), "slab+cluster 32M")

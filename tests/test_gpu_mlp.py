@@ -163,8 +163,8 @@ def test_forces_from_given_dEdG_vs_oracle(M, orc, om):
     ids = sim.ids.cpu().numpy()
     sim.dEdG[:n] = torch.tensor(dEdG[ids].astype(np.float32), device="cuda")
     ev = torch.zeros(8, dtype=torch.float64, device="cuda")
-    M.md_forces_mlp(L, n, sim.xs, sim.row_cap, sim.idx, sim.count, sim.mlp, None, sim.dEdG, None, sim.f, ev,
-                    M.MD_MLP_REUSE | M.MD_ENERGY, sim.ws)
+    M.md_forces_mlp(L, n, sim.xs, sim.row_cap, sim.idx, sim.count, sim.mlp, None, sim.dEdG, None, None, None, sim.f,
+                    ev, M.MD_MLP_REUSE | M.MD_ENERGY, sim.ws)
     fg = sim.forces()
     err = np.linalg.norm(fg - fo) / np.linalg.norm(fo)
     print(f"MLP pass-2 force error (normwise) {err:.3e}")
@@ -204,6 +204,33 @@ def test_forces_full_vs_oracle(M, orc, om):
     ev = sim.ev.cpu().numpy()
     assert ev[0] == pytest.approx(float(np.sum(eg.astype(np.float32).astype(np.float64))), rel=1e-6)
     assert abs(ev[0] - eo.sum()) < 0.5 * abs(eo.sum() - e64.sum()) + 1e-4 * n
+
+
+def test_compact_list_holds_the_pairs_within_rc(M, orc, om):
+    """Pass 1's compact rows are exactly the neighbours closer than rc (as
+    sets, in input ids); pass 2 on the compact list equals pass 2 on the
+    full list bit for bit."""
+    from paper_1611_00075_amd import mlp as P
+    x, L = _system(21, 5, drop=2, sigma=0.2)
+    x = orc.wrap(x, L)
+    n = len(x)
+    _, bits = _params(om, 22)
+    sim = _mlp_sim(M, x, L, P.spec(), bits.cuda())
+    sim.compute_forces()
+    ids = sim.ids.cpu().numpy()
+    rows = M.ell_rows(n, sim.row_cap, sim.idx_in, sim.cnt_in)
+    off, idx = orc.neighbors_brute(x, L, 5.0)
+    for k in range(n):
+        got = np.sort(ids[rows[k]])
+        want = idx[off[ids[k]]:off[ids[k] + 1]]
+        assert np.array_equal(got, want), k
+    f_full = torch.zeros_like(sim.f)
+    f_comp = torch.zeros_like(sim.f)
+    for f, li, lc in ((f_full, sim.idx, sim.count), (f_comp, sim.idx_in, sim.cnt_in)):
+        M.md_forces_mlp(L, n, sim.xs, sim.row_cap, li, lc, sim.mlp, None, sim.dEdG, None, None, None, f, sim.ev,
+                        M.MD_MLP_REUSE, sim.ws)
+    assert torch.equal(f_comp[:, :n], sim.f[:, :n])
+    assert torch.allclose(f_full[:, :n], f_comp[:, :n], rtol=1e-5, atol=1e-6)
 
 
 def test_forces_deterministic_and_md_run_path(M, orc, om):
