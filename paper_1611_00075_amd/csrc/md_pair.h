@@ -93,27 +93,32 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
 // at byte q * 256 + 4 * lane: one lane offset plus an immediate per load.
 // Per iteration each lane reads U entries, then their U positions (xs_r,
 // 16 bytes per atom, WORDS = 3 or 4 words read), then calls
-// body(pj, t) with the U positions of entries t + 8 u.  Entries past the
-// row end are read from the row's tail or as zero past the block and must
-// be masked by the body (t + 8 u >= cnt); their position loads stay inside
-// the bounded xs buffer whatever index they hold.
+// body(pj, t) with the U positions of entries t + 8 u.  For entries past
+// the row end both loads are given an offset outside their buffer, so they
+// move no data and return zero; the body masks them (t + 8 u >= cnt).
 template <int U, int WORDS, typename Body>
 __device__ __forceinline__ void walk_buf(const __amdgpu_buffer_rsrc_t &xs_r, const __amdgpu_buffer_rsrc_t &row_r,
                                          int32_t cnt, int sub, Body &&body)
 {
+    constexpr uint32_t kOut = 0xfffffff0u;   // beyond any buffer here
     uint32_t off = (threadIdx.x % kWave) * 4u;
     for (int32_t t = sub; t < cnt; t += U * kSlice, off += U * 256u) {
+        bool ok[U];
         uint32_t j[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) j[u] = __builtin_amdgcn_raw_buffer_load_b32(row_r, off + u * 256u, 0, 0);
+        for (int u = 0; u < U; ++u) {
+            ok[u] = t + u * kSlice < cnt;
+            j[u] = __builtin_amdgcn_raw_buffer_load_b32(row_r, ok[u] ? off + u * 256u : kOut, 0, 0);
+        }
         uint4 pj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            const uint32_t o = ok[u] ? j[u] << 4 : kOut;
             if (WORDS == 4) {
-                const auto v = __builtin_amdgcn_raw_buffer_load_b128(xs_r, j[u] << 4, 0, 0);
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(xs_r, o, 0, 0);
                 pj[u] = make_uint4(v[0], v[1], v[2], v[3]);
             } else {
-                const auto v = __builtin_amdgcn_raw_buffer_load_b96(xs_r, j[u] << 4, 0, 0);
+                const auto v = __builtin_amdgcn_raw_buffer_load_b96(xs_r, o, 0, 0);
                 pj[u] = make_uint4(v[0], v[1], v[2], 0u);
             }
         }
