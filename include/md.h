@@ -135,8 +135,10 @@ int md_scale_positions(const md_box_t *box, int64_t n, const double *x,
  * entry e < count[i] <= row_cap is stored at
  *     idx[(i/8 * row_cap/8 + e/8) * 64 + (i%8) * 8 + e%8],
  * i.e. the rows of a slice are interleaved in blocks of 8 entries, so idx
- * holds ceil(n / 8) * 8 * row_cap int32 (sorted atom indices). */
+ * holds ceil(n / 8) * 8 * row_cap int32 (sorted atom indices).  row_cap is
+ * at most MD_MAX_ROW_CAP. */
 #define MD_SLICE 8
+#define MD_MAX_ROW_CAP (1 << 24)
 
 /* Full Verlet lists (Sec. 3.3): row i holds every j != i with
  * r_ij^2 < r_list^2, r_ij^2 = (dx*dx + dy*dy) + dz*dz of the minimum-image

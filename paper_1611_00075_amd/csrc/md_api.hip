@@ -205,7 +205,8 @@ int md_build_neighbors(const md_grid_t *grid, int64_t n, const double *x, const 
                        int32_t row_cap, int32_t *idx, int32_t *count, int32_t *max_count, int32_t *needed, void *ws,
                        size_t ws_bytes, void *stream)
 {
-    if (!grid_ok(grid) || n < 0 || n > kMaxAtoms || !cell_start || !max_count || row_cap < 1 || row_cap % 8)
+    if (!grid_ok(grid) || n < 0 || n > kMaxAtoms || !cell_start || !max_count || row_cap < 1 || row_cap % 8 ||
+        row_cap > MD_MAX_ROW_CAP)
         return MD_ERR_ARG;
     if (n > 0 && (!x || !idx || !count)) return MD_ERR_ARG;
     WsLayout w;
@@ -218,7 +219,8 @@ int md_forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t
                  void *ws, size_t ws_bytes, void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
-    if (!lj || !(lj->rc > 0.0) || !(lj->sigma > 0.0) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8)
+    if (!lj || !(lj->rc > 0.0) || !(lj->sigma > 0.0) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8 ||
+        row_cap > MD_MAX_ROW_CAP)
         return MD_ERR_ARG;
     if (flags & ~(MD_ENERGY | MD_PAIR_FP64 | MD_NO_COMPENSATE)) return MD_ERR_ARG;
     if (n > 0 && (!idx || !count || !f)) return MD_ERR_ARG;
@@ -235,7 +237,8 @@ int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t row_cap,
                   double *ev, int32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
-    if (!fs || !(fs->d > 0.0) || !(fs->c > 0.0) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8)
+    if (!fs || !(fs->d > 0.0) || !(fs->c > 0.0) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8 ||
+        row_cap > MD_MAX_ROW_CAP)
         return MD_ERR_ARG;
     if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE)) return MD_ERR_ARG;
     if (n > 0 && (!xs || !idx || !count || !rho || !fprime || !f)) return MD_ERR_ARG;
@@ -271,7 +274,8 @@ int md_forces_mlp(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t ro
                   void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
-    if (!mlp_ok(mlp) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8) return MD_ERR_ARG;
+    if (!mlp_ok(mlp) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8 || row_cap > MD_MAX_ROW_CAP)
+        return MD_ERR_ARG;
     if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE | MD_MLP_REUSE)) return MD_ERR_ARG;
     const bool reuse = flags & MD_MLP_REUSE;
     if (!reuse && row_cap > MD_MLP_MAX_ROW) return MD_ERR_ARG;
@@ -345,7 +349,8 @@ int md_run(md_system_t *sys, int64_t steps, void *stream)
     if (sys->flags & ~(MD_PAIR_FP64 | MD_NO_COMPENSATE)) return MD_ERR_ARG;
     if (sys->potential != MD_POT_LJ && (sys->flags & MD_PAIR_FP64)) return MD_ERR_ARG;
     if (sys->potential == MD_POT_MLP && !mlp_ok(&sys->mlp)) return MD_ERR_ARG;
-    if (sys->row_cap < 8 || sys->row_cap % 8 || (sys->phase != 0 && sys->phase != 1)) return MD_ERR_ARG;
+    if (sys->row_cap < 8 || sys->row_cap % 8 || sys->row_cap > MD_MAX_ROW_CAP || (sys->phase != 0 && sys->phase != 1))
+        return MD_ERR_ARG;
     for (int a = 0; a < 3; ++a)
         if (sys->grid.L[a] != sys->box.L[a]) return MD_ERR_ARG;
     const bool f64 = sys->flags & MD_PAIR_FP64;

@@ -7,6 +7,7 @@
 // contraction (the library is built with -ffp-contract=off), so cell
 // assignments and neighbour sets are reproducible bit for bit.
 #include "md_common.h"
+#include "md_pair.h"
 
 namespace md {
 
@@ -224,35 +225,151 @@ __device__ __forceinline__ double minimg_sel(double d, double L, double hL)
     return d - t;
 }
 
-constexpr int kNbWaveTile = 128;       // candidates staged per wave at once
-constexpr int kNbWaves = kBlock / kWave;
+constexpr int kNbChunks = 4;           // 64-candidate chunks held in registers at once
+constexpr int kNbWaves = 1;            // wavefronts (cells) per block
+constexpr int kNbBlock = kNbWaves * kWave;
 
-// Per-wave LDS state.
+// Per-wave LDS state: the stencil's cell ranges and the home atoms'
+// positions (read back as broadcasts).
 struct NbWaveLds {
-    double sx[kNbWaveTile], sy[kNbWaveTile], sz[kNbWaveTile];
-    int32_t sj[kNbWaveTile];
+    double hx[kWave], hy[kWave], hz[kWave];
     int32_t rstart[kMaxStencil], rbase[kMaxStencil + 1];
 };
 
-// One wavefront per cell (Morton rank), four cells per block, no block-wide
-// barriers.  The atoms of the up to 27 (125) neighbouring cells are
-// contiguous runs of the sorted arrays; the wave stages them in LDS tiles of
-// 128 and tests one home atom against 64 candidates at a time, compacting
-// hits with a ballot straight into the sliced-ELL rows (entry e of atom i at
+// A tile of candidates in registers: lane l holds candidates l, 64 + l, ...
+struct NbTile {
+    double x[kNbChunks], y[kNbChunks], z[kNbChunks];
+    int32_t j[kNbChunks];
+};
+
+// Home atom i (position xi, yi, zi; r entries so far) against the first NC
+// chunks of the tile: every hit is appended to the row at r in candidate
+// order; returns the new row length.  All chunks are tested before any is
+// stored, so the NC chains are independent; a lane without a hit stores to
+// an offset past the row's buffer, which drops the store.
+template <int NC, bool INTERIOR>
+__device__ __forceinline__ uint32_t nb_home(const NbTile &T, double xi, double yi, double zi, int32_t i, uint32_t r,
+                                            __amdgpu_buffer_rsrc_t row, double rl2, const GridArgs &g)
+{
+    bool hit[NC];
+    uint64_t mk[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double dx = T.x[c] - xi, dy = T.y[c] - yi, dz = T.z[c] - zi;
+        if (!INTERIOR) {
+            dx = minimg_sel(dx, g.L[0], g.hL[0]);
+            dy = minimg_sel(dy, g.L[1], g.hL[1]);
+            dz = minimg_sel(dz, g.L[2], g.hL[2]);
+        }
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        hit[c] = (T.j[c] != i) && (r2 < rl2);
+        mk[c] = __builtin_amdgcn_ballot_w64(hit[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const uint32_t e = __builtin_amdgcn_mbcnt_hi(uint32_t(mk[c] >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo(uint32_t(mk[c]), r));
+        // entry e of the row at byte (e / 8) * 256 + (e % 8) * 4
+        const uint32_t off = hit[c] ? (e << 2) + __umul24(e >> 3, 224u) : 0xfffffff0u;
+        __builtin_amdgcn_raw_buffer_store_b32(T.j[c], row, off, 0, 0);
+        r += uint32_t(__popcll(mk[c]));
+    }
+    return r;
+}
+
+// The home batches of one cell against its stencil's candidates (tile by
+// tile); returns the longest row of the cell.
+template <bool INTERIOR>
+__device__ __forceinline__ int32_t nb_cell(NbWaveLds &L, int64_t n, const double *x, const GridArgs &g, double rl2,
+                                           int32_t h0, int32_t h1, int32_t m, int32_t total, int32_t row_cap,
+                                           int32_t *idx, int32_t *count)
+{
+    const int lane = threadIdx.x % kWave;
+    int top = 1;                              // highest power of two <= m
+    while (2 * top <= m) top *= 2;
+    int32_t longest = 0;
+    const double inf = __builtin_inf();
+    // bytes of one row seen as a buffer: its last entry (row_cap - 1) ends there
+    const uint32_t row_bytes = uint32_t(row_cap) * 32u - 224u;
+
+    for (int32_t hb = h0; hb < h1; hb += kWave) {
+        const int32_t hn = min(kWave, h1 - hb);
+        const int32_t hl = hb + min(lane, hn - 1);
+        L.hx[lane] = x[hl];
+        L.hy[lane] = x[n + hl];
+        L.hz[lane] = x[2 * n + hl];
+        // first int32 of the lane's home row (slice block + position in the slice)
+        const int64_t row_l = int64_t(hl >> 3) * row_cap * 8 + (hl & 7) * 8;
+        wave_sync();
+        int32_t run_l = 0;                                // row length of home atom `lane`
+        for (int32_t t0 = 0; t0 < total; t0 += kNbChunks * kWave) {
+            const int nch = min(kNbChunks, (total - t0 + kWave - 1) / kWave);
+            NbTile T;
+#pragma unroll
+            for (int c = 0; c < kNbChunks; ++c) {
+                const int32_t gq = t0 + c * kWave + lane;
+                T.j[c] = -1;
+                T.x[c] = T.y[c] = T.z[c] = inf;
+                if (c < nch && gq < total) {
+                    // last range k with rbase[k] <= gq; rbase[m] = total never is
+                    int k = 0;
+                    for (int s = top; s > 0; s >>= 1) {
+                        const int t = min(k + s, m);
+                        k = L.rbase[t] <= gq ? t : k;
+                    }
+                    const int32_t j = L.rstart[k] + (gq - L.rbase[k]);
+                    T.j[c] = j;
+                    T.x[c] = x[j];
+                    T.y[c] = x[n + j];
+                    T.z[c] = x[2 * n + j];
+                }
+            }
+            for (int32_t h = 0; h < hn; ++h) {
+                const int32_t i = hb + h;
+                const uint32_t r = uint32_t(__builtin_amdgcn_readlane(run_l, h));
+                const int64_t ro = int64_t(uint32_t(__builtin_amdgcn_readlane(int32_t(row_l), h))) |
+                                   (int64_t(__builtin_amdgcn_readlane(int32_t(row_l >> 32), h)) << 32);
+                const auto row = make_rsrc(idx + ro, row_bytes);
+                const double xi = L.hx[h], yi = L.hy[h], zi = L.hz[h];
+                uint32_t rn;
+                switch (nch) {
+                case 4: rn = nb_home<4, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
+                case 3: rn = nb_home<3, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
+                case 2: rn = nb_home<2, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
+                default: rn = nb_home<1, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
+                }
+                if (lane == h) run_l = int32_t(rn);
+            }
+        }
+        if (lane < hn) count[hb + lane] = run_l;
+        longest = max(longest, lane < hn ? run_l : 0);
+        wave_sync();
+    }
+    return longest;
+}
+
+// One wavefront per cell (Morton rank), no block-wide barriers.  The atoms
+// of the up to 27 (125) neighbouring cells are contiguous runs of the
+// sorted arrays; the wave walks them in tiles of 256 candidates held in
+// registers (past the last candidate, candidates at infinity), and tests
+// one home atom against 64 candidates at a time, compacting hits with a
+// ballot straight into the sliced-ELL rows (entry e of atom i at
 // idx[(i/8 * row_cap/8 + e/8) * 64 + (i%8) * 8 + e%8]).  Row order: stencil
-// cell, then sorted
-// index.  Rows longer than row_cap are counted but truncated; the longest
-// row length is folded into *max_count.
+// cell, then sorted index.  Rows longer than row_cap are counted but
+// truncated (the row is written through a buffer whose range ends at entry
+// row_cap, so stores past it are dropped); the longest row length is folded
+// into *max_count.
 //
 // Interior cells (no stencil cell wraps around the box and nc >= 2 reach + 2
 // on every axis) use the plain difference x_j - x_i: every candidate is then
 // closer than half a box, so the minimum-image correction of the definition
-// never applies and the result is bitwise the same.
-__global__ __launch_bounds__(kBlock) void k_neighbors(int64_t n, const double *x, GridArgs g, double rl2,
-                                                      int64_t n_cells, const int32_t *cell_start,
-                                                      const int32_t *rank_xyz, const int32_t *lin2rank,
-                                                      int32_t row_cap, int32_t *idx, int32_t *count,
-                                                      int32_t *max_count)
+// never applies and the result is bitwise the same.  A padding candidate
+// gives +inf in every branch, so it never passes r^2 < r_list^2.
+__global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double *x, GridArgs g, double rl2,
+                                                        int64_t n_cells, const int32_t *cell_start,
+                                                        const int32_t *rank_xyz, const int32_t *lin2rank,
+                                                        int32_t row_cap, int32_t *idx, int32_t *count,
+                                                        int32_t *max_count)
 {
     __shared__ NbWaveLds lds_all[kNbWaves];
     const int lane = threadIdx.x % kWave, wave = uni(threadIdx.x / kWave);
@@ -301,66 +418,14 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(int64_t n, const double *x
     }
     if (lane == 0) L.rbase[0] = 0;
     wave_sync();
-    const int32_t total = carry;
-    int32_t longest = 0;
-
-    for (int32_t hb = h0; hb < h1; hb += kWave) {
-        const int32_t hn = min(kWave, h1 - hb);
-        // home positions, fetched once and broadcast with shuffles
-        const int32_t hl = hb + min(lane, hn - 1);
-        const double xl = x[hl], yl = x[n + hl], zl = x[2 * n + hl];
-        int32_t run_l = 0;                                // row length of home atom `lane`
-        for (int32_t t0 = 0; t0 < total; t0 += kNbWaveTile) {
-            const int32_t tn = min(kNbWaveTile, total - t0);
-            wave_sync();
-            for (int32_t q = lane; q < tn; q += kWave) {
-                const int32_t gq = t0 + q;
-                int lo = 0, hi = m - 1;           // last range with rbase <= gq
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (L.rbase[mid] <= gq) lo = mid; else hi = mid - 1;
-                }
-                const int32_t j = L.rstart[lo] + (gq - L.rbase[lo]);
-                L.sj[q] = j;
-                L.sx[q] = x[j];
-                L.sy[q] = x[n + j];
-                L.sz[q] = x[2 * n + j];
-            }
-            wave_sync();
-            for (int32_t h = 0; h < hn; ++h) {
-                const int32_t i = hb + h;
-                const double xi = lane_f64(xl, h), yi = lane_f64(yl, h), zi = lane_f64(zl, h);
-                int32_t r = __builtin_amdgcn_readlane(run_l, h);
-                int32_t *row = idx + (int64_t(i >> 3) * row_cap * 8 + (i & 7) * 8);
-                for (int32_t c0 = 0; c0 < tn; c0 += kWave) {
-                    const int32_t q = c0 + lane;
-                    bool hit = false;
-                    if (q < tn) {
-                        double dx = L.sx[q] - xi, dy = L.sy[q] - yi, dz = L.sz[q] - zi;
-                        if (!interior) {
-                            dx = minimg_sel(dx, g.L[0], g.hL[0]);
-                            dy = minimg_sel(dy, g.L[1], g.hL[1]);
-                            dz = minimg_sel(dz, g.L[2], g.hL[2]);
-                        }
-                        const double r2 = (dx * dx + dy * dy) + dz * dz;
-                        hit = (L.sj[q] != i) && (r2 < rl2);
-                    }
-                    const uint64_t mask = __ballot(hit);
-                    if (hit) {
-                        const int e = r + __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
-                        if (e < row_cap) row[int64_t(e >> 3) * 64 + (e & 7)] = L.sj[q];
-                    }
-                    r += __popcll(mask);
-                }
-                if (lane == h) run_l = r;
-            }
-        }
-        if (lane < hn) count[hb + lane] = run_l;
-        longest = max(longest, lane < hn ? run_l : 0);
-    }
+    int32_t longest = interior ? nb_cell<true>(L, n, x, g, rl2, h0, h1, m, carry, row_cap, idx, count)
+                               : nb_cell<false>(L, n, x, g, rl2, h0, h1, m, carry, row_cap, idx, count);
     for (int o = kWave / 2; o > 0; o >>= 1) longest = max(longest, __shfl_xor(longest, o, kWave));
-    if (lane == 0) atomicMax(max_count, longest);
+    // *max_count only grows, so a wave whose longest row does not exceed a
+    // value already there has nothing to add: the check keeps the atomics on
+    // this one word (which the L2 serialises) to a few per launch
+    if (lane == 0 && longest > __hip_atomic_load(max_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(max_count, longest);
 }
 
 int build_neighbors(const md_grid_t *grid, int64_t n, const double *x, const int32_t *cell_start, int32_t row_cap,
@@ -380,7 +445,7 @@ int build_neighbors(const md_grid_t *grid, int64_t n, const double *x, const int
     if (rc) return rc;
     const uint32_t nb = uint32_t((grid->n_cells + kNbWaves - 1) / kNbWaves);
     if (n > 0) {
-        hipLaunchKernelGGL(k_neighbors, dim3(nb), dim3(kBlock), 0, s, n, x, g, rl2, grid->n_cells, cell_start,
+        hipLaunchKernelGGL(k_neighbors, dim3(nb), dim3(kNbBlock), 0, s, n, x, g, rl2, grid->n_cells, cell_start,
                            ws_ptr<int32_t>(ws, w.rank2lin), ws_ptr<int32_t>(ws, w.lin2rank), row_cap, idx, count,
                            max_count);
         MD_HIP_TRY(hipGetLastError());

@@ -21,6 +21,7 @@ MD_ERR_NONFINITE, MD_ERR_HIP, MD_ERR_WORKSPACE = -4, -5, -6
 MD_ENERGY, MD_PAIR_FP64, MD_NO_COMPENSATE, MD_MLP_REUSE = 0x1, 0x2, 0x4, 0x8
 MD_KICK_DRIFT, MD_KICK = 1, 2
 MD_SLICE = 8
+MD_MAX_ROW_CAP = 1 << 24
 
 
 class Box(C.Structure):

@@ -50,6 +50,8 @@ CASES = [
     ("gas_reach2", (12.0, 9.0, 10.0), 2.5, 900, 3, 2),
     ("gas_tiny_nc2", (3.0, 3.0, 3.0), 1.45, 37, 4, 1),
     ("gas_ragged", (17.3, 11.1, 13.7), 2.8, 3001, 5, 1),
+    # about 130 atoms per cell: several home batches and candidate tiles per cell
+    ("gas_dense", (16.0, 16.0, 16.0), 3.9, 8000, 6, 1),
 ]
 
 
@@ -146,6 +148,14 @@ def test_abi_rejects_bad_arguments(M):
     assert e.value.code == M.MD_ERR_BOX
     with pytest.raises(M.MDError):
         M.md_grid_init([5.0, 5.0, 5.0], 1.0, reach=3)
+    # row capacity past the largest the list layout addresses
+    g, ws, xd, cell, perm, cs = _bin(M, np.zeros((0, 3)), np.array([10.0, 10.0, 10.0]), 2.8)
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mx = torch.zeros(1, dtype=torch.int32, device="cuda")
+    idx = torch.empty(8, dtype=torch.int32, device="cuda")
+    with pytest.raises(M.MDError) as e:
+        M.md_build_neighbors(g, 0, xd, cs, M.MD_MAX_ROW_CAP + 8, idx, cnt, mx, ws)
+    assert e.value.code == M.MD_ERR_ARG
 
 
 # ---------------------------------------------------------------------------
