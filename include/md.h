@@ -338,7 +338,7 @@ int md_mlp_train_step(int64_t batch, const int32_t *sel, const float *G,
  *   rebuild rule: moved more than half the skin since the last build);
  *   status[1] gets bit 0 set when a new position is not finite.  status is
  *   never cleared by the library.  If xs is not NULL, the scaled
- *   coordinates are rewritten from the new positions (xs[4i+3] untouched).
+ *   coordinates are rewritten from the new positions (xs[4i+3] set to 0).
  * MD_KICK: if ke is not NULL, *ke (device) = 1/2 mass sum |v|^2 over the
  *   updated velocities, reduced in FP64 in a fixed order. */
 int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x,

@@ -29,6 +29,14 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G)
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// Device-side skip of a speculative launch: a gated kernel returns at once
+// when *flag == tag (flag written earlier on the same stream).
+struct Gate {
+    const int32_t *flag = nullptr;
+    int32_t tag = 0;
+};
+__device__ __forceinline__ bool gated(const Gate &g) { return g.flag && *g.flag == g.tag; }
+
 // Orders the LDS accesses of one wavefront around this point (the lanes of a
 // wave exchange data through LDS without a block barrier).
 __device__ __forceinline__ void wave_sync()
@@ -134,9 +142,10 @@ int scale_positions(const md_box_t *, int64_t, const double *, uint32_t *, hipSt
 int build_neighbors(const md_grid_t *, int64_t, const double *, const int32_t *, int32_t, int32_t *, int32_t *,
                     int32_t *, int32_t *, void *, const WsLayout &, hipStream_t);
 int forces_lj(const md_box_t *, int64_t, const double *, const uint32_t *, int32_t, const int32_t *, const int32_t *,
-              const md_lj_t *, void *, double *, int32_t, void *, const WsLayout &, hipStream_t);
+              const md_lj_t *, void *, double *, int32_t, void *, const WsLayout &, hipStream_t, Gate = {});
 int forces_eam(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, const int32_t *, const md_fs_t *,
-               float *, float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t);
+               float *, float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t,
+               Gate = {});
 int integrate(int32_t, const md_box_t *, int64_t, double *, double *, const void *, double, double, double,
               const double *, double, int32_t *, int32_t, uint32_t *, double *, int32_t, void *, const WsLayout &,
               hipStream_t);
@@ -145,7 +154,7 @@ int mlp_descriptors(const md_box_t *, int64_t, const uint32_t *, int32_t, const 
 int mlp_eval(int64_t, const float *, const md_mlp_t *, const uint16_t *, float *, float *, hipStream_t);
 int forces_mlp(const md_box_t *, int64_t, const uint32_t *, int32_t, const int32_t *, const int32_t *,
                const md_mlp_t *, const uint16_t *, float *, int32_t *, int32_t *, float *, float *, double *, int32_t,
-               void *, const WsLayout &, hipStream_t);
+               void *, const WsLayout &, hipStream_t, Gate = {});
 size_t mlp_workspace_bytes(int64_t batch);
 int mlp_moments(int64_t, const float *, double *, void *, hipStream_t);
 // gradient of the batch loss (grad, loss may be NULL); with adam, an Adam

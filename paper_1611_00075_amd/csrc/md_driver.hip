@@ -3,10 +3,12 @@
 //
 // Per step: kick + drift with the rebuild check (the closing half kick of the
 // previous step is fused in when steps follow each other), a one-thread
-// kernel publishes the step's rebuild flag into pinned host memory, the host
-// polls that word, rebuilds the lists when some atom has moved more than
-// half the skin, evaluates the forces, and either opens the next step or
-// closes this one with a half kick.
+// kernel publishes the step's rebuild flag into pinned host memory, the
+// force evaluation of the new positions is queued behind it (gated on the
+// device by the same flag), the host polls the flag word, and when some atom
+// has moved more than half the skin it rebuilds the lists and evaluates the
+// forces again; then it either opens the next step or closes this one with
+// a half kick.
 #include <chrono>
 #include <thread>
 
@@ -27,14 +29,22 @@ __global__ void k_publish(const int32_t *status, int32_t *host, int32_t tag)
 
 namespace {
 
-// Waits for the rebuild flag of step `tag`; returns MD_OK and sets *moved,
-// *bad.  Fast path: the publish kernel writes device-visible pinned memory
-// that the host polls; otherwise a copy and a stream synchronisation.
-int wait_flag(md_system_t *sys, int32_t *host_dev, int32_t tag, hipStream_t s, bool *moved, bool *bad)
+// The rebuild flag of step `tag`, in two halves so that device work can be
+// queued between them.  Fast path: the publish kernel writes device-visible
+// pinned memory that the host polls; otherwise a copy and a stream
+// synchronisation.
+int post_flag(md_system_t *sys, int32_t *host_dev, int32_t tag, hipStream_t s)
+{
+    if (!host_dev) return MD_OK;
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(1), 0, s, sys->status, host_dev, tag);
+    MD_HIP_TRY(hipGetLastError());
+    return MD_OK;
+}
+
+// Waits for the flag posted for step `tag`; sets *moved, *bad.
+int read_flag(md_system_t *sys, int32_t *host_dev, int32_t tag, hipStream_t s, bool *moved, bool *bad)
 {
     if (host_dev) {
-        hipLaunchKernelGGL(k_publish, dim3(1), dim3(1), 0, s, sys->status, host_dev, tag);
-        MD_HIP_TRY(hipGetLastError());
         volatile int32_t *h = sys->host_status;
         const auto t0 = std::chrono::steady_clock::now();
         for (uint64_t spin = 0; h[0] != tag; ++spin) {
@@ -83,26 +93,31 @@ int rebuild(md_system_t *sys, const WsLayout &w, hipStream_t s)
     return MD_OK;
 }
 
-int forces(md_system_t *sys, const WsLayout &w, hipStream_t s)
+// The force evaluation of the current positions; with a gate, the kernels
+// do nothing when the gate's flag is set on the device.
+int forces(md_system_t *sys, const WsLayout &w, hipStream_t s, Gate gate = {})
 {
     if (sys->potential == MD_POT_LJ)
         return forces_lj(&sys->box, sys->n, sys->x, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->lj, sys->f,
-                         nullptr, sys->flags & (MD_PAIR_FP64 | MD_NO_COMPENSATE), sys->ws, w, s);
+                         nullptr, sys->flags & (MD_PAIR_FP64 | MD_NO_COMPENSATE), sys->ws, w, s, gate);
     if (sys->potential == MD_POT_MLP)
         return forces_mlp(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->mlp, sys->mlp_w,
                           sys->dEdG, sys->idx_in, sys->cnt_in, nullptr, static_cast<float *>(sys->f), nullptr,
-                          sys->flags & MD_NO_COMPENSATE, sys->ws, w, s);
+                          sys->flags & MD_NO_COMPENSATE, sys->ws, w, s, gate);
     return forces_eam(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->fs, sys->rho,
                       sys->fprime, static_cast<float *>(sys->f), nullptr, nullptr, sys->flags & MD_NO_COMPENSATE,
-                      sys->ws, w, s);
+                      sys->ws, w, s, gate);
 }
 
 // Optional timing of the force evaluations: one event pair per evaluation,
-// read back once the stream has passed it (the next flag wait or the end).
+// kept in recording order and read back once the stream has passed it.  A
+// speculative evaluation that the device skipped is dropped unread.
 struct ForceTimer {
+    static constexpr int kSlots = 4;
     bool on = false;
-    hipEvent_t ev[2][2] = {};
-    int pending = -1;   // slot with a recorded, unread pair
+    hipEvent_t ev[kSlots][2] = {};
+    int queue[kSlots] = {};   // recorded, unread pairs, oldest first
+    int queued = 0;
     int next = 0;
     bool init(bool want)
     {
@@ -123,23 +138,35 @@ struct ForceTimer {
     {
         if (on) (void)hipEventRecord(ev[next][0], s);
     }
-    void stop(hipStream_t s)
+    void stop(md_system_t *sys, hipStream_t s)
     {
         if (!on) return;
+        if (queued == kSlots) collect(sys, true, 0);   // keep a free slot
         (void)hipEventRecord(ev[next][1], s);
-        pending = next;
-        next ^= 1;
+        queue[queued++] = next;
+        next = (next + 1) % kSlots;
     }
-    void collect(md_system_t *sys, bool wait)
+    void drop_last()
     {
-        if (!on || pending < 0) return;
-        if (wait) (void)hipEventSynchronize(ev[pending][1]);
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, ev[pending][0], ev[pending][1]) == hipSuccess) {
-            sys->force_ms += ms;
-            ++sys->force_calls;
+        if (on && queued > 0) --queued;
+    }
+    // Reads back all but the `keep` most recent pairs (waiting for them when
+    // `wait`; otherwise the caller knows the stream has passed them).
+    void collect(md_system_t *sys, bool wait, int keep)
+    {
+        if (!on) return;
+        int k = 0;
+        for (; k < queued - keep; ++k) {
+            const int p = queue[k];
+            if (wait) (void)hipEventSynchronize(ev[p][1]);
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[p][0], ev[p][1]) == hipSuccess) {
+                sys->force_ms += ms;
+                ++sys->force_calls;
+            }
         }
-        pending = -1;
+        for (int j = k; j < queued; ++j) queue[j - k] = queue[j];
+        queued -= k;
     }
 };
 
@@ -167,36 +194,52 @@ int run(md_system_t *sys, int64_t steps, hipStream_t s)
         if ((rc = forces(sys, w, s))) return rc;
     }
     int64_t done = 0;
+    // Speculative force evaluation: after each drift the forces of the new
+    // positions are queued before the host has read the rebuild flag, gated
+    // on the device by that flag (status[0] == tag: some atom moved more than
+    // half the skin).  When the flag is set the gated kernels do nothing and
+    // the host rebuilds and evaluates again; otherwise the evaluation is the
+    // step's.
+    bool ready = false;   // forces of the in-flight step already queued
+    const auto drift = [&](double h, int32_t tag) -> int {
+        int r = kick_drift(&sys->box, sys->n, sys->x, sys->v, sys->f, f64, h, sys->dt, sys->xref, sys->half_skin_sq,
+                           sys->status, tag, xs, s);
+        if (r || (r = post_flag(sys, host_dev, tag, s))) return r;
+        timer.start(s);
+        if ((r = forces(sys, w, s, Gate{sys->status, tag}))) return r;
+        timer.stop(sys, s);
+        if ((r = read_flag(sys, host_dev, tag, s, &moved, &bad))) return r;
+        ready = !moved && !bad;
+        if (!ready) timer.drop_last();
+        // the flag came after every earlier evaluation on the stream
+        timer.collect(sys, false, ready ? 1 : 0);
+        return MD_OK;
+    };
     for (;;) {
         if (sys->phase == 0) {
             if (done >= steps) break;
-            const int32_t tag = int32_t(sys->step + 1);
-            if ((rc = kick_drift(&sys->box, sys->n, sys->x, sys->v, sys->f, f64, hk, sys->dt, sys->xref,
-                                 sys->half_skin_sq, sys->status, tag, xs, s)))
-                return rc;
+            if ((rc = drift(hk, int32_t(sys->step + 1)))) return rc;
             sys->phase = 1;
-            if ((rc = wait_flag(sys, host_dev, tag, s, &moved, &bad))) return rc;
             if (bad) return MD_ERR_NONFINITE;
             sys->need_build |= moved ? 1 : 0;
         }
-        // a step is in flight: positions drifted, forces stale
+        // a step is in flight: positions drifted, forces stale unless queued
         if (sys->need_build) {
+            ready = false;
             if ((rc = rebuild(sys, w, s))) return rc;
             sys->need_build = 0;
         }
-        timer.start(s);
-        if ((rc = forces(sys, w, s))) return rc;
-        timer.stop(s);
+        if (!ready) {
+            timer.start(s);
+            if ((rc = forces(sys, w, s))) return rc;
+            timer.stop(sys, s);
+        }
+        ready = false;
         ++sys->step;
         ++done;
         if (done < steps) {
             // closing half kick of this step fused with the opening one of the next
-            const int32_t tag = int32_t(sys->step + 1);
-            if ((rc = kick_drift(&sys->box, sys->n, sys->x, sys->v, sys->f, f64, 2.0 * hk, sys->dt, sys->xref,
-                                 sys->half_skin_sq, sys->status, tag, xs, s)))
-                return rc;
-            if ((rc = wait_flag(sys, host_dev, tag, s, &moved, &bad))) return rc;
-            timer.collect(sys, false);   // the stream has passed the force evaluation
+            if ((rc = drift(2.0 * hk, int32_t(sys->step + 1)))) return rc;
             if (bad) return MD_ERR_NONFINITE;
             sys->need_build |= moved ? 1 : 0;
         } else {
@@ -206,7 +249,7 @@ int run(md_system_t *sys, int64_t steps, hipStream_t s)
             sys->phase = 0;
         }
     }
-    timer.collect(sys, true);
+    timer.collect(sys, true, 0);
     return MD_OK;
 }
 

@@ -31,6 +31,7 @@ struct LJ32 {
     float ax, ay, az;       // L_a / 2^32 (non-cubic boxes)
     float len;              // length unit of the displacements (s or 1)
     float rc2, sig2, eps4, eps24;  // rc^2, sigma^2 in that unit; 4 eps; 24 eps / unit
+    Gate gate;
 };
 
 template <int TPA, int U, bool CUBIC, bool ENERGY, bool COMP>
@@ -39,6 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restr
                                                  const int32_t *__restrict__ count, LJ32 p, float *__restrict__ f,
                                                  double *__restrict__ part)
 {
+    if (gated(p.gate)) return;
     static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const SliceLane sl = slice_lane(blk);
@@ -102,6 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restr
 struct LJ64 {
     double L[3], hL[3];
     double rc2, sig2, eps4, eps24;
+    Gate gate;
 };
 
 __device__ __forceinline__ double minimg64(double d, double L, double hL)
@@ -119,6 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_lj64(int64_t n, const double *__rest
                                                  const int32_t *__restrict__ count, LJ64 p, double *__restrict__ f,
                                                  double *__restrict__ part)
 {
+    if (gated(p.gate)) return;
     static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const SliceLane sl = slice_lane(blk);
@@ -184,6 +188,7 @@ struct FS32 {
     float len;              // length unit of the displacements (s or 1)
     float d2u, c2u;         // d^2, c^2 in that unit
     float d, c, p0, p1, p2, A;  // physical
+    Gate gate;
 };
 
 // pass 1: rho_i = sum psi(r_ij), then F_i = -A sqrt(rho_i), F'_i; F'_i is
@@ -195,6 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
                                                     float *__restrict__ rho, float *__restrict__ fprime,
                                                     double *__restrict__ part)
 {
+    if (gated(p.gate)) return;
     static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const SliceLane sl = slice_lane(blk);
@@ -254,6 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
                                                       const float *__restrict__ rho, float *__restrict__ f,
                                                       float *__restrict__ e_atom, double *__restrict__ part)
 {
+    if (gated(p.gate)) return;
     static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const SliceLane sl = slice_lane(blk);
@@ -362,7 +369,7 @@ static void dispatch_lj32(bool e, bool c, uint32_t gb, hipStream_t s, int64_t n,
 
 int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *xs, int32_t cap, const int32_t *idx,
               const int32_t *cnt, const md_lj_t *lj, void *f, double *ev, int32_t flags, void *ws, const WsLayout &w,
-              hipStream_t s)
+              hipStream_t s, Gate gate)
 {
     const List l{cap, idx, cnt};
     const bool energy = flags & MD_ENERGY;
@@ -386,6 +393,7 @@ int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *x
             p.sig2 = lj->sigma * lj->sigma;
             p.eps4 = 4.0 * lj->eps;
             p.eps24 = 24.0 * lj->eps;
+            p.gate = gate;
             double *fd = static_cast<double *>(f);
             if (energy)
                 hipLaunchKernelGGL((k_lj64<kTPA, true>), dim3(gb), dim3(kBlock), 0, s, n, x, cap, idx, cnt, p, fd,
@@ -408,6 +416,7 @@ int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *x
             p.sig2 = float(lj->sigma * lj->sigma / (u * u));
             p.eps4 = float(4.0 * lj->eps);
             p.eps24 = float(24.0 * lj->eps / u);
+            p.gate = gate;
             const uint4 *q = reinterpret_cast<const uint4 *>(xs);
             float *ff = static_cast<float *>(f);
             const bool comp = !(flags & MD_NO_COMPENSATE);
@@ -442,7 +451,7 @@ static void dispatch_eam(bool e, bool c, uint32_t gb, hipStream_t s, int64_t n, 
 
 int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
                const md_fs_t *fs, float *rho, float *fprime, float *f, float *e_atom, double *ev, int32_t flags,
-               void *ws, const WsLayout &w, hipStream_t s)
+               void *ws, const WsLayout &w, hipStream_t s, Gate gate)
 {
     const List l{cap, idx, cnt};
     const bool energy = flags & MD_ENERGY;
@@ -467,6 +476,7 @@ int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const 
     p.p1 = float(fs->c1 + 2.0 * fs->c2 * fs->c);
     p.p2 = float(fs->c2);
     p.A = float(fs->A);
+    p.gate = gate;
     uint4 *q = reinterpret_cast<uint4 *>(xs);
     if (n > 0) {
         if (cubic) dispatch_eam<kTPA, true>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, e_atom, part1, part2);

@@ -46,13 +46,10 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(int64_t n, double *__rest
             const double dz = minimg_d(p[2] - xref[2 * n + i], a.L[2], a.hL[2]);
             moved = ((dx * dx + dy * dy) + dz * dz) > a.half_skin_sq;
         }
-        if (xs) {
-            uint4 q = xs[i];
-            q.x = uint32_t(uint64_t(__double2ll_rn(p[0] * a.k[0])));
-            q.y = uint32_t(uint64_t(__double2ll_rn(p[1] * a.k[1])));
-            q.z = uint32_t(uint64_t(__double2ll_rn(p[2] * a.k[2])));
-            xs[i] = q;
-        }
+        if (xs)   // whole 16-byte words, nothing read back
+            xs[i] = make_uint4(uint32_t(uint64_t(__double2ll_rn(p[0] * a.k[0]))),
+                               uint32_t(uint64_t(__double2ll_rn(p[1] * a.k[1]))),
+                               uint32_t(uint64_t(__double2ll_rn(p[2] * a.k[2]))), 0u);
     }
     // one store per wave that saw the condition (idempotent values)
     if (__ballot(moved) && (threadIdx.x % kWave) == 0) status[0] = a.tag;

@@ -97,6 +97,7 @@ struct MlpArgs {
     float phi;              // pi / (2 rc)
     float iw2, cw;          // 1 / w^2, dmu / w^2
     float mean[kIn], inv_std[kIn];
+    Gate gate;
 };
 
 MlpArgs make_args(const md_box_t *box, const md_mlp_t *m)
@@ -363,6 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_desc(int64_t n, MlpArgs p, const
                                                      const int32_t *__restrict__ count, float *__restrict__ G,
                                                      int32_t *__restrict__ idx_in, int32_t *__restrict__ cnt_in)
 {
+    if (gated(p.gate)) return;
     extern __shared__ float seg_lds[];
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const SliceLane sl = slice_lane(blk);
@@ -392,6 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_net(int64_t n, MlpArgs p, const 
                                                     const uint16_t *__restrict__ w, float *__restrict__ e_atom,
                                                     float *dEdG, double *__restrict__ part)
 {
+    if (gated(p.gate)) return;
     __shared__ WeightsLds L;
     __shared__ double red[kBlock / kWave];
     stage_weights(L, w, p);
@@ -452,6 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_force(int64_t n, MlpArgs p, cons
                                                       const float4 *__restrict__ dEdG, float *__restrict__ f,
                                                       double *__restrict__ part)
 {
+    if (gated(p.gate)) return;
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const SliceLane sl = slice_lane(blk);
     const int64_t i = sl.i;
@@ -818,7 +822,7 @@ int mlp_eval(int64_t n, const float *G, const md_mlp_t *mlp, const uint16_t *w, 
 int forces_mlp(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t cap, const int32_t *idx,
                const int32_t *count, const md_mlp_t *mlp, const uint16_t *w, float *dEdG, int32_t *idx_in,
                int32_t *cnt_in, float *e_atom, float *f, double *ev, int32_t flags, void *ws, const WsLayout &wl,
-               hipStream_t s)
+               hipStream_t s, Gate gate)
 {
     const bool energy = flags & MD_ENERGY;
     const bool comp = !(flags & MD_NO_COMPENSATE);
@@ -828,7 +832,8 @@ int forces_mlp(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t cap, 
     const uint32_t g1 = n > 0 && !reuse ? atom_grid(n) : 0;
     const uint32_t g2 = n > 0 ? slice_blocks(n) : 0;
     if (int64_t(g1) > wl.red_blocks || int64_t(g2) > wl.red_blocks) return MD_ERR_WORKSPACE;
-    const MlpArgs a = make_args(box, mlp);
+    MlpArgs a = make_args(box, mlp);
+    a.gate = gate;
     const uint4 *q = reinterpret_cast<const uint4 *>(xs);
     if (n > 0) {
         if (!reuse) {
