@@ -404,9 +404,13 @@ typedef struct md_system {
  * system) the lists and forces are built first; otherwise f must hold the
  * forces of x.  Per-atom arrays stay in the library's sorted order; ids maps
  * them to input order.
- * The host waits once per step for the 4-byte rebuild flag: when host_status
- * is pinned host memory the device publishes the flag there and the host
- * polls it, otherwise it copies the flag and synchronises the stream.
+ * The host waits once per step for the 4-byte rebuild flag, and once per
+ * build for the longest list row: when host_status is pinned host memory
+ * the device publishes them there (words 0-2: flag, word 3: longest row) and
+ * the host polls them, otherwise it copies them and synchronises the stream.
+ * Each step's force evaluation is queued before the host has read the flag
+ * (and after a build, before it has read the longest row); the kernels skip
+ * themselves on the device when the flag is set or a row overflowed.
  * Returns MD_OK when all steps are done and the state is at a step boundary.
  * MD_ERR_CAPACITY: a list row exceeded row_cap; row_cap_needed holds the
  * longest row, a step is in flight (phase 1); grow idx, set row_cap and call

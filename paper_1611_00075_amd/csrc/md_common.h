@@ -30,12 +30,18 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G)
 }
 
 // Device-side skip of a speculative launch: a gated kernel returns at once
-// when *flag == tag (flag written earlier on the same stream).
+// when *flag == tag or *over > limit (words written earlier on the same
+// stream).
 struct Gate {
     const int32_t *flag = nullptr;
     int32_t tag = 0;
+    const int32_t *over = nullptr;
+    int32_t limit = 0;
 };
-__device__ __forceinline__ bool gated(const Gate &g) { return g.flag && *g.flag == g.tag; }
+__device__ __forceinline__ bool gated(const Gate &g)
+{
+    return (g.flag && *g.flag == g.tag) || (g.over && *g.over > g.limit);
+}
 
 // Orders the LDS accesses of one wavefront around this point (the lanes of a
 // wave exchange data through LDS without a block barrier).

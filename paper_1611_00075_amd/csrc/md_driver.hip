@@ -27,6 +27,15 @@ __global__ void k_publish(const int32_t *status, int32_t *host, int32_t tag)
     h[0] = tag;
 }
 
+// The longest row of the list just built, into host word 3 (which the host
+// set negative before queueing this kernel).
+__global__ void k_publish_longest(const int32_t *max_count, int32_t *host)
+{
+    volatile int32_t *h = host;
+    h[3] = *max_count;
+    __threadfence_system();
+}
+
 namespace {
 
 // The rebuild flag of step `tag`, in two halves so that device work can be
@@ -68,7 +77,10 @@ int read_flag(md_system_t *sys, int32_t *host_dev, int32_t tag, hipStream_t s, b
     return MD_OK;
 }
 
-int rebuild(md_system_t *sys, const WsLayout &w, hipStream_t s)
+// Bins, sorts and builds the lists without waiting for the longest row:
+// check_build reads it once the force evaluation (gated on the device by the
+// same row length) is queued behind the build.
+int rebuild(md_system_t *sys, const WsLayout &w, hipStream_t s, int32_t *host_dev)
 {
     const int64_t n = sys->n;
     const size_t b3 = size_t(3 * n) * sizeof(double);
@@ -84,11 +96,43 @@ int rebuild(md_system_t *sys, const WsLayout &w, hipStream_t s)
         MD_HIP_TRY(hipMemcpyAsync(sys->xref, sys->x, b3, hipMemcpyDeviceToDevice, s));
         if (!(sys->flags & MD_PAIR_FP64) && (rc = scale_positions(&sys->box, n, sys->x, sys->xs, s))) return rc;
     }
-    int32_t longest = 0;
     rc = build_neighbors(&sys->grid, n, sys->x, sys->cell_start, sys->row_cap, sys->idx, sys->count, sys->max_count,
-                         &longest, sys->ws, w, s);
-    if (rc == MD_ERR_CAPACITY) sys->row_cap_needed = longest;
+                         nullptr, sys->ws, w, s);
     if (rc) return rc;
+    if (host_dev) {
+        reinterpret_cast<volatile int32_t *>(sys->host_status)[3] = -1;
+        hipLaunchKernelGGL(k_publish_longest, dim3(1), dim3(1), 0, s, sys->max_count, host_dev);
+        MD_HIP_TRY(hipGetLastError());
+    }
+    return MD_OK;
+}
+
+// Waits for the longest row of the last build: MD_ERR_CAPACITY (with
+// row_cap_needed) when it exceeds row_cap.
+int check_build(md_system_t *sys, int32_t *host_dev, hipStream_t s)
+{
+    int32_t longest = 0;
+    if (host_dev) {
+        volatile int32_t *h = sys->host_status;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (uint64_t spin = 0; h[3] < 0; ++spin) {
+            if ((spin & 4095) == 4095) {
+                const hipError_t e = hipStreamQuery(s);
+                if (e != hipSuccess && e != hipErrorNotReady) return MD_ERR_HIP;
+                if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120)) return MD_ERR_HIP;
+                std::this_thread::yield();
+            }
+        }
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        longest = h[3];
+    } else {
+        MD_HIP_TRY(hipMemcpyAsync(&longest, sys->max_count, sizeof(longest), hipMemcpyDeviceToHost, s));
+        MD_HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (longest > sys->row_cap) {
+        sys->row_cap_needed = longest;
+        return MD_ERR_CAPACITY;
+    }
     ++sys->builds;
     return MD_OK;
 }
@@ -188,10 +232,13 @@ int run(md_system_t *sys, int64_t steps, hipStream_t s)
     bool moved = false, bad = false;
     ForceTimer timer;
     if (!timer.init(sys->timing != 0)) return MD_ERR_HIP;
+    // forces of a fresh build, skipped on the device when a row overflowed
+    const Gate fits{nullptr, 0, sys->max_count, sys->row_cap};
     if (sys->phase == 0 && sys->need_build) {
-        if ((rc = rebuild(sys, w, s))) return rc;
+        if ((rc = rebuild(sys, w, s, host_dev))) return rc;
+        if ((rc = forces(sys, w, s, fits))) return rc;
+        if ((rc = check_build(sys, host_dev, s))) return rc;
         sys->need_build = 0;
-        if ((rc = forces(sys, w, s))) return rc;
     }
     int64_t done = 0;
     // Speculative force evaluation: after each drift the forces of the new
@@ -224,15 +271,22 @@ int run(md_system_t *sys, int64_t steps, hipStream_t s)
             sys->need_build |= moved ? 1 : 0;
         }
         // a step is in flight: positions drifted, forces stale unless queued
-        if (sys->need_build) {
+        const bool built = sys->need_build != 0;
+        if (built) {
             ready = false;
-            if ((rc = rebuild(sys, w, s))) return rc;
-            sys->need_build = 0;
+            if ((rc = rebuild(sys, w, s, host_dev))) return rc;
         }
         if (!ready) {
             timer.start(s);
-            if ((rc = forces(sys, w, s))) return rc;
+            if ((rc = forces(sys, w, s, built ? fits : Gate{}))) return rc;
             timer.stop(sys, s);
+        }
+        if (built) {
+            if ((rc = check_build(sys, host_dev, s))) {
+                timer.drop_last();
+                return rc;
+            }
+            sys->need_build = 0;
         }
         ready = false;
         ++sys->step;
