@@ -140,6 +140,11 @@ int md_scale_positions(const md_box_t *box, int64_t n, const double *x,
 #define MD_SLICE 8
 #define MD_MAX_ROW_CAP (1 << 24)
 
+/* Largest n the FP32 pair paths (md_forces_lj without MD_PAIR_FP64,
+ * md_forces_eam, the MLP entry points, md_run without MD_PAIR_FP64) accept:
+ * they read the scaled coordinates through one 32-bit byte range. */
+#define MD_MAX_ATOMS_FP32 ((1 << 28) - 1)
+
 /* Full Verlet lists (Sec. 3.3): row i holds every j != i with
  * r_ij^2 < r_list^2, r_ij^2 = (dx*dx + dy*dy) + dz*dz of the minimum-image
  * displacement dx = x_j - x_i (shifted by L when |dx| > L/2), in FP64 with

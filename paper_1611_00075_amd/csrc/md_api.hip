@@ -13,6 +13,9 @@ namespace {
 inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
 constexpr int64_t kMaxAtoms = 2147483646;  // int32 atom indices
+// the FP32 pair kernels address the scaled coordinates (16 B per atom)
+// through one 32-bit buffer range
+constexpr int64_t kMaxAtomsXs = MD_MAX_ATOMS_FP32;
 
 bool box_ok(const md_box_t *b)
 {
@@ -226,6 +229,7 @@ int md_forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t
     if (n > 0 && (!idx || !count || !f)) return MD_ERR_ARG;
     if (n > 0 && (flags & MD_PAIR_FP64) && !x) return MD_ERR_ARG;
     if (n > 0 && !(flags & MD_PAIR_FP64) && !xs) return MD_ERR_ARG;
+    if (!(flags & MD_PAIR_FP64) && n > kMaxAtomsXs) return MD_ERR_ARG;
     if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
     WsLayout w;
     if (int rc = ws_check_n(n, ws, ws_bytes, w)) return rc;
@@ -237,7 +241,7 @@ int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t row_cap,
                   double *ev, int32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
-    if (!fs || !(fs->d > 0.0) || !(fs->c > 0.0) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8 ||
+    if (!fs || !(fs->d > 0.0) || !(fs->c > 0.0) || n < 0 || n > kMaxAtomsXs || row_cap < 1 || row_cap % 8 ||
         row_cap > MD_MAX_ROW_CAP)
         return MD_ERR_ARG;
     if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE)) return MD_ERR_ARG;
@@ -254,7 +258,7 @@ int md_mlp_descriptors(const md_box_t *box, int64_t n, const uint32_t *xs, int32
                        const int32_t *count, const md_mlp_t *mlp, float *G, void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
-    if (!mlp_ok(mlp) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8 || row_cap > MD_MLP_MAX_ROW)
+    if (!mlp_ok(mlp) || n < 0 || n > kMaxAtomsXs || row_cap < 1 || row_cap % 8 || row_cap > MD_MLP_MAX_ROW)
         return MD_ERR_ARG;
     if (n > 0 && (!xs || !idx || !count || !G)) return MD_ERR_ARG;
     return mlp_descriptors(box, n, xs, row_cap, idx, count, mlp, G, as_stream(stream));
@@ -274,7 +278,7 @@ int md_forces_mlp(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t ro
                   void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
-    if (!mlp_ok(mlp) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8 || row_cap > MD_MAX_ROW_CAP)
+    if (!mlp_ok(mlp) || n < 0 || n > kMaxAtomsXs || row_cap < 1 || row_cap % 8 || row_cap > MD_MAX_ROW_CAP)
         return MD_ERR_ARG;
     if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE | MD_MLP_REUSE)) return MD_ERR_ARG;
     const bool reuse = flags & MD_MLP_REUSE;
@@ -354,6 +358,7 @@ int md_run(md_system_t *sys, int64_t steps, void *stream)
     for (int a = 0; a < 3; ++a)
         if (sys->grid.L[a] != sys->box.L[a]) return MD_ERR_ARG;
     const bool f64 = sys->flags & MD_PAIR_FP64;
+    if (!f64 && sys->n > kMaxAtomsXs) return MD_ERR_ARG;
     if (sys->n > 0) {
         if (!sys->x || !sys->v || !sys->xref || !sys->scratch || !sys->ids || !sys->ids_scratch || !sys->f ||
             !sys->cell || !sys->perm || !sys->cell_start || !sys->idx || !sys->count || !sys->max_count ||

@@ -22,6 +22,7 @@ MD_ENERGY, MD_PAIR_FP64, MD_NO_COMPENSATE, MD_MLP_REUSE = 0x1, 0x2, 0x4, 0x8
 MD_KICK_DRIFT, MD_KICK = 1, 2
 MD_SLICE = 8
 MD_MAX_ROW_CAP = 1 << 24
+MD_MAX_ATOMS_FP32 = (1 << 28) - 1
 
 
 class Box(C.Structure):

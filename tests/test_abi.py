@@ -81,3 +81,30 @@ def test_product_path_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(md, "LIB_PATH", "/nonexistent/libmd.so")
     with pytest.raises(RuntimeError, match="not built"):
         md.lib()
+
+
+def test_size_limits_rejected_before_any_device_work(lib):
+    """Atom counts past the FP32 paths' 32-bit position range and row
+    capacities past MD_MAX_ROW_CAP are argument errors, returned before any
+    pointer is used (NULL buffers here; no GPU needed)."""
+    from paper_1611_00075_amd import md
+    vp = C.c_void_p
+    box = md.Box((C.c_double * 3)(20.0, 20.0, 20.0))
+    big = md.MD_MAX_ATOMS_FP32 + 1
+    lib.md_forces_lj.argtypes = [C.POINTER(md.Box), C.c_int64, vp, vp, C.c_int32, vp, vp, C.POINTER(md.LJ),
+                                 vp, vp, C.c_int32, vp, C.c_size_t, vp]
+    lj = md.LJ(1.0, 1.0, 2.5)
+    assert lib.md_forces_lj(C.byref(box), big, None, None, 64, None, None, C.byref(lj), None, None, 0,
+                            None, 0, None) == md.MD_ERR_ARG
+    lib.md_forces_eam.argtypes = [C.POINTER(md.Box), C.c_int64, vp, C.c_int32, vp, vp, C.POINTER(md.FS), vp,
+                                  vp, vp, vp, vp, C.c_int32, vp, C.c_size_t, vp]
+    fs = md.FS(1.0, 4.0, 4.0, 1.0, 0.0, 0.0)
+    assert lib.md_forces_eam(C.byref(box), big, None, 64, None, None, C.byref(fs), None, None, None, None, None, 0,
+                             None, 0, None) == md.MD_ERR_ARG
+    assert lib.md_forces_eam(C.byref(box), 10, None, md.MD_MAX_ROW_CAP + 8, None, None, C.byref(fs), None, None,
+                             None, None, None, 0, None, 0, None) == md.MD_ERR_ARG
+    g = md.md_grid_init([20.0, 20.0, 20.0], 2.8, 1)
+    lib.md_build_neighbors.argtypes = [C.POINTER(md.Grid), C.c_int64, vp, vp, C.c_int32, vp, vp, vp,
+                                       C.POINTER(C.c_int32), vp, C.c_size_t, vp]
+    assert lib.md_build_neighbors(C.byref(g), 0, None, vp(8), md.MD_MAX_ROW_CAP + 8, None, None, vp(8), None,
+                                  None, 0, None) == md.MD_ERR_ARG
