@@ -13,8 +13,10 @@ steps untimed).
 
 Printed: one JSON line with the metric, a roofline object for the dominant
 kernel (the LJ force kernel, algorithmic bytes per launch / mean launch time
-from HIP events on the launch stream), the FP64 oracle's rate on this host
-(cpu_baseline) and the other workloads of the metric (EAM metal, FP64 LJ).
+from HIP events on the launch stream, against the published 8 TB/s and
+against a device-to-device copy measured in the same run), the FP64
+oracle's rate on this host (cpu_baseline) and the other workloads of the
+metric (EAM metal, the 32 M-atom slab, FP64 LJ, the learned potential).
 """
 from __future__ import annotations
 
@@ -233,6 +235,27 @@ def pairs_within(sim, rc, torch, chunk=131072):
     return total
 
 
+def copy_bandwidth(torch, gib=2, reps=10):
+    """Achievable HBM rate on this GPU: a device-to-device copy of `gib` GiB
+    (read + write counted), timed with HIP events -- the measured peak the
+    kernels' rates are also compared with."""
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(st)
+    torch.cuda.synchronize()
+    gbs = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,6 +320,9 @@ def main():
     }
     del sim
     torch.cuda.empty_cache()
+    copy_gbs = copy_bandwidth(torch)
+    result["roofline"]["copy_GBs"] = copy_gbs
+    result["roofline"]["frac_of_copy"] = achieved / copy_gbs
 
     extra = {}
     thermal = None
@@ -318,6 +344,7 @@ def main():
                 "ms_per_step": 1e3 * r3["seconds"] / st3, "rebuilds": r3["rebuilds"],
                 "forces_ms": f3, "forces_GBs": b3 / (f3 * 1e-3) / 1e9,
                 "forces_frac_hbm": b3 / (f3 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "forces_frac_copy": b3 / (f3 * 1e-3) / 1e9 / copy_gbs,
                 "phases_ms_per_call_api": {k: v[0] for k, v in r3["phases"].items()},
             }
         _, ke3 = sim3.energies()
@@ -338,6 +365,7 @@ def main():
             "ms_per_step": 1e3 * r4["seconds"] / 100, "rebuilds": r4["rebuilds"], "list_entries": sim4.n_pairs,
             "forces_ms": r4["force_ms"], "forces_GBs": b4 / (r4["force_ms"] * 1e-3) / 1e9,
             "forces_frac_hbm": b4 / (r4["force_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "forces_frac_copy": b4 / (r4["force_ms"] * 1e-3) / 1e9 / copy_gbs,
             "slab_atoms": s4.meta["slab_atoms"], "cluster_atoms": s4.meta["cluster_atoms"],
         }
         del sim4, s4

@@ -77,6 +77,8 @@ def _declare(L):
                                C.POINTER(LJParams), _dp, _dp, _dp, _dp]
     L.or_forces_eam.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
                                 C.POINTER(FSParams), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_forces_tb.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
+                               C.POINTER(TBParams), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_md_run.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                             C.POINTER(MDParams), C.c_int64, _dp, _dp, _dp]
     L.or_md_run.restype = C.c_int64
@@ -170,6 +172,25 @@ def forces_eam(x, L, off, idx, fs: dict):
                         _p(np.ascontiguousarray(off, np.int64), _i64p),
                         _p(np.ascontiguousarray(idx, np.int32), _i32p), C.byref(prm),
                         _p(rho), _p(fp), *[_p(c) for c in f], _p(ea), _p(ev))
+    return dict(rho=rho, fprime=fp, f=np.stack(f, axis=1), e_atom=ea, ev=ev)
+
+
+class TBParams(C.Structure):
+    _fields_ = [("A", C.c_double), ("xi", C.c_double), ("p", C.c_double), ("q", C.c_double),
+                ("r0", C.c_double), ("rs", C.c_double), ("rc", C.c_double)]
+
+
+def forces_tb(x, L, off, idx, tb: dict):
+    """FP64 second-moment tight-binding potential: dict as forces_eam."""
+    xs = _soa(x)
+    n = len(xs[0])
+    f = [np.zeros(n) for _ in range(3)]
+    rho, fp, ea, ev = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(8)
+    prm = TBParams(*[float(tb[k]) for k in ("A", "xi", "p", "q", "r0", "rs", "rc")])
+    lib().or_forces_tb(n, _p(_box(L)), *[_p(c) for c in xs],
+                       _p(np.ascontiguousarray(off, np.int64), _i64p),
+                       _p(np.ascontiguousarray(idx, np.int32), _i32p), C.byref(prm),
+                       _p(rho), _p(fp), *[_p(c) for c in f], _p(ea), _p(ev))
     return dict(rho=rho, fprime=fp, f=np.stack(f, axis=1), e_atom=ea, ev=ev)
 
 

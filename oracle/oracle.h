@@ -103,6 +103,26 @@ void or_forces_eam(int64_t n, const double L[3], const double *x,
                    double *fprime, double *fx, double *fy, double *fz,
                    double *e_atom, double ev[8]);
 
+/* Second-moment tight-binding potential in the form of Eqs. (1)-(2): the
+ * exponential density and pair functions and square-root embedding that
+ * Sec. 3.1 names for its copper potential,
+ *   psi(r) = xi^2 exp(-2q (r/r0 - 1)) S(r),  Phi(r) = 2A exp(-p (r/r0 - 1)) S(r),
+ *   F(rho) = -sqrt(rho)  (F = F' = 0 at rho = 0),
+ * with the smooth cutoff S = 1 for r <= rs, S = 0 for r >= rc and
+ * S = 1 - x^3 (10 - 15 x + 6 x^2), x = (r - rs)/(rc - rs), in between.
+ * (The factor 2 in Phi makes the paper's 1/2 sum_{i != j} Phi the sum over
+ * atoms of sum_j A exp(...).)  Same three steps and outputs as
+ * or_forces_eam; e_atom = F(rho_i) + 1/2 sum_j Phi(r_ij). */
+typedef struct {
+    double A, xi, p, q, r0, rs, rc;
+} or_tb_t;
+
+void or_forces_tb(int64_t n, const double L[3], const double *x,
+                  const double *y, const double *z, const int64_t *offsets,
+                  const int32_t *idx, const or_tb_t *p, double *rho,
+                  double *fprime, double *fx, double *fy, double *fz,
+                  double *e_atom, double ev[8]);
+
 /* ---- velocity-Verlet molecular dynamics (Sec. 3.3) ---- */
 
 enum { OR_POT_LJ = 0, OR_POT_EAM = 1 };

@@ -36,6 +36,13 @@ CU_A0 = 3.615
 FS_CU = dict(A=0.6904081156, d=4.4, c=3.25,
              c0=12.35488532, c1=-9.40961636, c2=1.84672514)
 
+# Second-moment tight-binding (exponential) potential of the same form as the
+# paper's copper potential, with a synthetic parameter set: p and q chosen,
+# r0 = the nearest-neighbour distance at a = 3.615 A, smooth cutoff between
+# the third (4.43 A) and fourth (5.11 A) neighbour shells, and A, xi solved
+# from the cohesive energy 3.54 eV and zero pressure at a = 3.615 A.
+TB_CU = dict(A=0.1044093115, xi=1.3137843239, p=10.0, q=2.5, r0=2.5561910140, rs=4.5, rc=5.0)
+
 FCC_BASIS = np.array([[0.0, 0.0, 0.0],
                       [0.5, 0.5, 0.0],
                       [0.5, 0.0, 0.5],
