@@ -353,6 +353,27 @@ def main():
         del sim3
         torch.cuda.empty_cache()
     if args.only == "all":
+        # ---- second-moment tight-binding metal, 4 M atoms -------------------
+        log("TB crystal: generating")
+        s5 = inputs.eam_cu()
+        sim5 = Simulation(s5.L, s5.x, s5.v, potential="tb", tb=inputs.TB_CU, skin=1.0, dt=1.0,
+                          mass=inputs.CU_MASS_AMU, force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
+        log("TB crystal: running")
+        r5 = run_workload(sim5, 200, 10, torch)
+        f5 = r5["force_ms"]
+        b5 = eam_force_bytes(s5.n, sim5.n_pairs)
+        extra["tb_cu_fcc_100^3"] = {
+            "atoms": s5.n, "steps": 200, "value": s5.n * 200 / r5["seconds"], "unit": "atom-steps/s",
+            "ms_per_step": 1e3 * r5["seconds"] / 200, "rebuilds": r5["rebuilds"], "list_entries": sim5.n_pairs,
+            "forces_ms": f5, "forces_GBs": b5 / (f5 * 1e-3) / 1e9,
+            "forces_frac_hbm": b5 / (f5 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "forces_frac_copy": b5 / (f5 * 1e-3) / 1e9 / copy_gbs,
+            "potential": "second-moment tight-binding (exponential psi and Phi, sqrt embedding), "
+                         "synthetic Cu-like parameters, rc 5.0 A, list 6.0 A",
+            "phases_ms_per_call_api": {k: v[0] for k, v in r5["phases"].items()},
+        }
+        del sim5, s5
+        torch.cuda.empty_cache()
         # ---- LJ slab with a dense cluster, about 32 M atoms ----------------
         log("LJ slab + cluster: generating")
         s4 = inputs.lj_slab_cluster()

@@ -212,6 +212,27 @@ int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs,
                   float *e_atom, double *ev, int32_t flags, void *ws,
                   size_t ws_bytes, void *stream);
 
+/* Second-moment tight-binding potential in the form of Eqs. (1)-(2) with
+ * the exponential density and pair functions and square-root embedding
+ * that Sec. 3.1 names for its copper potential:
+ *   psi(r) = xi^2 exp(-2q (r/r0 - 1)) S(r),  Phi(r) = 2A exp(-p (r/r0 - 1)) S(r),
+ *   F(rho) = -sqrt(rho)  (F = F' = 0 at rho = 0),
+ * S = 1 for r <= rs, 0 for r >= rc, 1 - x^3 (10 - 15 x + 6 x^2) with
+ * x = (r - rs)/(rc - rs) in between (0 < rs < rc).  Energies in the unit of
+ * A and xi, lengths in the unit of r0. */
+typedef struct md_tb {
+    double A, xi, p, q, r0, rs, rc;
+} md_tb_t;
+
+/* The same three steps, kernels and outputs as md_forces_eam, with psi,
+ * Phi and F of md_tb_t (Phi in place of V; e_atom[i] = F(rho_i) +
+ * 1/2 sum_j Phi(r_ij)).  The list must reach rc. */
+int md_forces_tb(const md_box_t *box, int64_t n, uint32_t *xs,
+                 int32_t row_cap, const int32_t *idx, const int32_t *count,
+                 const md_tb_t *tb, float *rho, float *fprime, float *f,
+                 float *e_atom, double *ev, int32_t flags, void *ws,
+                 size_t ws_bytes, void *stream);
+
 /* ---- steps a8/a9: learned descriptor-MLP potential ----
  *
  * A learned stand-in for the embedded-atom energy of Eqs. (1)-(2): like
@@ -357,6 +378,7 @@ int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x,
 #define MD_POT_LJ  0
 #define MD_POT_EAM 1
 #define MD_POT_MLP 2
+#define MD_POT_TB  3
 
 /* One system for md_run.  The caller fills every field (device buffers are
  * caller-owned; sizes as for the calls above) and keeps the struct between
@@ -386,7 +408,7 @@ typedef struct md_system {
     size_t ws_bytes;
     int32_t row_cap;
     int32_t row_cap_needed;     /* out: set with MD_ERR_CAPACITY */
-    int32_t potential;          /* MD_POT_LJ, MD_POT_EAM or MD_POT_MLP */
+    int32_t potential;          /* MD_POT_LJ, MD_POT_EAM, MD_POT_MLP or MD_POT_TB */
     int32_t flags;              /* MD_PAIR_FP64 (LJ only), MD_NO_COMPENSATE */
     int32_t need_build;         /* 1: build lists (and forces) before stepping */
     int32_t phase;              /* 0: at a step boundary; 1: a step is in flight */
@@ -398,12 +420,14 @@ typedef struct md_system {
     const uint16_t *mlp_w;      /* MD_POT_MLP: MD_MLP_NPARAM bfloat16 parameters */
     float *dEdG;                /* MD_POT_MLP: [16n] scratch */
     int32_t *idx_in, *cnt_in;   /* MD_POT_MLP: compact list scratch, sized as idx, count */
+    md_tb_t tb;                 /* MD_POT_TB (rho, fprime as for MD_POT_EAM) */
 } md_system_t;
 
 /* Runs `steps` velocity-Verlet steps (Sec. 3.3) of the path: kick + drift
  * with the rebuild check, md_bin_cells + md_permute + md_scale_positions +
  * md_build_neighbors whenever some atom moved more than skin/2 since the
- * last build, forces (md_forces_lj, md_forces_eam or md_forces_mlp), kick.  Between two
+ * last build, forces (md_forces_lj, md_forces_eam, md_forces_mlp or
+ * md_forces_tb), kick.  Between two
  * steps the closing half kick and the next opening half kick are applied as
  * one kick with the same forces.  On entry with need_build set (a new
  * system) the lists and forces are built first; otherwise f must hold the

@@ -254,6 +254,30 @@ int md_forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t row_cap,
                       as_stream(stream));
 }
 
+static bool tb_ok(const md_tb_t *tb)
+{
+    return tb && tb->A > 0.0 && tb->xi > 0.0 && tb->p > 0.0 && tb->q > 0.0 && tb->r0 > 0.0 && tb->rs > 0.0 &&
+           tb->rc > tb->rs && std::isfinite(tb->A) && std::isfinite(tb->xi) && std::isfinite(tb->p) &&
+           std::isfinite(tb->q) && std::isfinite(tb->r0) && std::isfinite(tb->rc);
+}
+
+int md_forces_tb(const md_box_t *box, int64_t n, uint32_t *xs, int32_t row_cap, const int32_t *idx,
+                 const int32_t *count, const md_tb_t *tb, float *rho, float *fprime, float *f, float *e_atom,
+                 double *ev, int32_t flags, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!box_ok(box)) return MD_ERR_BOX;
+    if (!tb_ok(tb) || n < 0 || n > kMaxAtomsXs || row_cap < 1 || row_cap % 8 || row_cap > MD_MAX_ROW_CAP)
+        return MD_ERR_ARG;
+    if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE)) return MD_ERR_ARG;
+    if (n > 0 && (!xs || !idx || !count || !rho || !fprime || !f)) return MD_ERR_ARG;
+    if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
+    if (e_atom && !(flags & MD_ENERGY)) return MD_ERR_ARG;
+    WsLayout w;
+    if (int rc = ws_check_n(n, ws, ws_bytes, w)) return rc;
+    return forces_tb(box, n, xs, row_cap, idx, count, tb, rho, fprime, f, e_atom, ev, flags, ws, w,
+                     as_stream(stream));
+}
+
 int md_mlp_descriptors(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t row_cap, const int32_t *idx,
                        const int32_t *count, const md_mlp_t *mlp, float *G, void *stream)
 {
@@ -348,8 +372,10 @@ int md_run(md_system_t *sys, int64_t steps, void *stream)
 {
     if (!sys || steps < 0 || !box_ok(&sys->box) || !grid_ok(&sys->grid) || sys->n < 0 || sys->n > kMaxAtoms)
         return MD_ERR_ARG;
-    if (sys->potential != MD_POT_LJ && sys->potential != MD_POT_EAM && sys->potential != MD_POT_MLP)
+    if (sys->potential != MD_POT_LJ && sys->potential != MD_POT_EAM && sys->potential != MD_POT_MLP &&
+        sys->potential != MD_POT_TB)
         return MD_ERR_ARG;
+    if (sys->potential == MD_POT_TB && !tb_ok(&sys->tb)) return MD_ERR_ARG;
     if (sys->flags & ~(MD_PAIR_FP64 | MD_NO_COMPENSATE)) return MD_ERR_ARG;
     if (sys->potential != MD_POT_LJ && (sys->flags & MD_PAIR_FP64)) return MD_ERR_ARG;
     if (sys->potential == MD_POT_MLP && !mlp_ok(&sys->mlp)) return MD_ERR_ARG;
@@ -365,7 +391,8 @@ int md_run(md_system_t *sys, int64_t steps, void *stream)
             !sys->status)
             return MD_ERR_ARG;
         if (!f64 && !sys->xs) return MD_ERR_ARG;
-        if (sys->potential == MD_POT_EAM && (!sys->rho || !sys->fprime)) return MD_ERR_ARG;
+        if ((sys->potential == MD_POT_EAM || sys->potential == MD_POT_TB) && (!sys->rho || !sys->fprime))
+            return MD_ERR_ARG;
         if (sys->potential == MD_POT_MLP && (!sys->mlp_w || !sys->dEdG || !sys->idx_in || !sys->cnt_in))
             return MD_ERR_ARG;
     }

@@ -152,6 +152,9 @@ int forces_lj(const md_box_t *, int64_t, const double *, const uint32_t *, int32
 int forces_eam(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, const int32_t *, const md_fs_t *,
                float *, float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t,
                Gate = {});
+int forces_tb(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, const int32_t *, const md_tb_t *,
+              float *, float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t,
+              Gate = {});
 int integrate(int32_t, const md_box_t *, int64_t, double *, double *, const void *, double, double, double,
               const double *, double, int32_t *, int32_t, uint32_t *, double *, int32_t, void *, const WsLayout &,
               hipStream_t);

@@ -144,6 +144,10 @@ int forces(md_system_t *sys, const WsLayout &w, hipStream_t s, Gate gate = {})
     if (sys->potential == MD_POT_LJ)
         return forces_lj(&sys->box, sys->n, sys->x, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->lj, sys->f,
                          nullptr, sys->flags & (MD_PAIR_FP64 | MD_NO_COMPENSATE), sys->ws, w, s, gate);
+    if (sys->potential == MD_POT_TB)
+        return forces_tb(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->tb, sys->rho,
+                         sys->fprime, static_cast<float *>(sys->f), nullptr, nullptr, sys->flags & MD_NO_COMPENSATE,
+                         sys->ws, w, s, gate);
     if (sys->potential == MD_POT_MLP)
         return forces_mlp(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->mlp, sys->mlp_w,
                           sys->dEdG, sys->idx_in, sys->cnt_in, nullptr, static_cast<float *>(sys->f), nullptr,

@@ -1,4 +1,6 @@
-// Steps a4-a6: Lennard-Jones and embedded-atom forces over full Verlet lists.
+// Steps a4-a6: Lennard-Jones and embedded-atom forces over full Verlet lists
+// (the two-pass embedded-atom kernels serve both the Finnis-Sinclair form
+// and the exponential second-moment tight-binding form of Sec. 3.1).
 //
 // The pair loop of the paper (Sec. 2.2) visits each pair once and scatters
 // -F into f_j; the paper avoids the resulting write races with its cell-task
@@ -8,11 +10,12 @@
 //
 // Lists are sliced ELL: slices of 8 atoms whose rows are interleaved in
 // blocks of 8 entries.  A wave holds one slice, 8 consecutive lanes per atom,
-// so each load of 64 indices reads one contiguous 256-byte run.  Each lane fetches U list entries and then U
-// positions before using any, so U independent gathers per lane are in
-// flight.  The row is walked on a clamped index (the tail re-reads the last
-// entry and masks it out) so the loop has no divergent loads.  The 8
-// partial sums of an atom are combined in FP64 with lane shuffles.
+// so each load of 64 indices reads one contiguous 256-byte run.  Each lane
+// fetches U list entries and then U positions before using any, so U
+// independent gathers per lane are in flight.  Rows are walked with raw
+// buffer loads: a slot past the row's end gets an out-of-range offset,
+// which returns zeros without memory traffic, so no load is predicated.
+// The 8 partial sums of an atom are combined in FP64 with lane shuffles.
 //
 // FP32 path: displacements come from 32-bit scaled coordinates (fraction of
 // the box times 2^32, Sec. 4.1 "fetch"/"dist"): the integer difference is the
@@ -20,6 +23,8 @@
 // s = L/2^32 (cutoffs and constants are pre-scaled on the host); the unit
 // vector of a pair does not depend on the unit.  Pair arithmetic is FP32;
 // per-lane sums are Kahan-compensated unless MD_NO_COMPENSATE.
+#include <cmath>
+
 #include "md_pair.h"
 
 namespace md {
@@ -191,12 +196,90 @@ struct FS32 {
     Gate gate;
 };
 
+// Second-moment tight-binding form: psi = exp2(cq - kq r) S(r),
+// Phi = exp2(cp - kp r) S(r), F = -A sqrt(rho) with A = 1; the constants
+// fold xi^2, 2A, r0 and the exponents (kq = 2q log2(e)/r0, lq = 2q/r0, ...).
+struct TB32 {
+    float ax, ay, az;       // L_a / 2^32 (non-cubic boxes)
+    float len;              // length unit of the displacements (s or 1)
+    float cut2u;            // rc^2 in that unit
+    float rs, iw;           // switch start, 1 / (rc - rs)
+    float kq, cq, lq;       // density: exponent slope (base 2), offset, slope (base e)
+    float kp, cp, lp;       // pair function, likewise
+    float A;                // embedding prefactor (1)
+    Gate gate;
+};
+
+// ---- pair terms of the two forms ------------------------------------------
+// rho_term: psi(r) of a listed pair (0 when not counted); force_term: the
+// force factor g = -(dU/dr)/r_u (F_i = g d, d in the displacement unit) and
+// the pair energy of the pair, given fsum = F'_i + F'_j.
+
+struct PairOut {
+    float g, v;
+    bool in;
+};
+
+__device__ __forceinline__ float rho_term(const FS32 &p, float r2, bool valid)
+{
+    const float t = __builtin_amdgcn_sqrtf(r2) * p.len - p.d;
+    return (valid && r2 < p.d2u) ? t * t : 0.f;
+}
+
+__device__ __forceinline__ PairOut force_term(const FS32 &p, float r2, bool valid, float fsum)
+{
+    const bool in_d = valid && r2 < p.d2u, in_c = valid && r2 < p.c2u;
+    const float ru = __builtin_amdgcn_sqrtf(r2);
+    const float r = ru * p.len;
+    const float dpsi = in_d ? fsum * 2.f * (r - p.d) : 0.f;
+    const float t = r - p.c;
+    const float poly = __builtin_fmaf(__builtin_fmaf(p.p2, t, p.p1), t, p.p0);
+    const float dpoly = __builtin_fmaf(2.f * p.p2, t, p.p1);
+    const float dV = in_c ? t * __builtin_fmaf(t, dpoly, 2.f * poly) : 0.f;
+    float g = -(dpsi + dV) * __builtin_amdgcn_rcpf(ru);
+    g = in_d || in_c ? g : 0.f;
+    return {g, in_c ? t * t * poly : 0.f, in_d || in_c};
+}
+
+// S(r) and dS/dr of the smooth cutoff, branch-free (x clamped to [0, 1])
+__device__ __forceinline__ void tb_switch(const TB32 &p, float r, float &S, float &dS)
+{
+    const float x = fminf(fmaxf((r - p.rs) * p.iw, 0.f), 1.f);
+    const float x2 = x * x, y = 1.f - x;
+    S = __builtin_fmaf(-x2 * x, __builtin_fmaf(__builtin_fmaf(6.f, x, -15.f), x, 10.f), 1.f);
+    dS = -30.f * p.iw * x2 * y * y;
+}
+
+__device__ __forceinline__ float rho_term(const TB32 &p, float r2, bool valid)
+{
+    const float r = __builtin_amdgcn_sqrtf(r2) * p.len;
+    float S, dS;
+    tb_switch(p, r, S, dS);
+    const float psi = __builtin_amdgcn_exp2f(__builtin_fmaf(-p.kq, r, p.cq)) * S;
+    return (valid && r2 < p.cut2u) ? psi : 0.f;
+}
+
+__device__ __forceinline__ PairOut force_term(const TB32 &p, float r2, bool valid, float fsum)
+{
+    const bool in = valid && r2 < p.cut2u;
+    const float ru = __builtin_amdgcn_sqrtf(r2);
+    const float r = ru * p.len;
+    float S, dS;
+    tb_switch(p, r, S, dS);
+    const float eq = __builtin_amdgcn_exp2f(__builtin_fmaf(-p.kq, r, p.cq));
+    const float ep = __builtin_amdgcn_exp2f(__builtin_fmaf(-p.kp, r, p.cp));
+    const float dpsi = fsum * eq * __builtin_fmaf(-p.lq, S, dS);
+    const float dPhi = ep * __builtin_fmaf(-p.lp, S, dS);
+    const float g = -(dpsi + dPhi) * __builtin_amdgcn_rcpf(ru);
+    return {in ? g : 0.f, in ? ep * S : 0.f, in};
+}
+
 // pass 1: rho_i = sum psi(r_ij), then F_i = -A sqrt(rho_i), F'_i; F'_i is
 // stored in the fourth word of the scaled coordinates for pass 2's gather.
-template <int TPA, int U, bool CUBIC, bool ENERGY, bool COMP>
+template <class P, int TPA, int U, bool CUBIC, bool ENERGY, bool COMP>
 __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict__ xs,
                                                     int32_t cap, const int32_t *__restrict__ idx,
-                                                    const int32_t *__restrict__ count, FS32 p,
+                                                    const int32_t *__restrict__ count, P p,
                                                     float *__restrict__ rho, float *__restrict__ fprime,
                                                     double *__restrict__ part)
 {
@@ -219,9 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
                 float dx, dy, dz;
                 disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
                 const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                float t = __builtin_amdgcn_sqrtf(r2) * p.len - p.d;
-                t = (t0 + u * TPA < cnt && r2 < p.d2u) ? t : 0.f;
-                bs = __builtin_fmaf(t, t, bs);
+                bs += rho_term(p, r2, t0 + u * TPA < cnt);
             }
             acc_sum<COMP>(s, c, bs);
         });
@@ -253,10 +334,10 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
 }
 
 // pass 2: F_i = -sum_j [(F'_i + F'_j) psi'(r) + V'(r)] (r_i - r_j) / r
-template <int TPA, int U, bool CUBIC, bool ENERGY, bool COMP>
+template <class P, int TPA, int U, bool CUBIC, bool ENERGY, bool COMP>
 __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__restrict__ xs,
                                                       int32_t cap, const int32_t *__restrict__ idx,
-                                                      const int32_t *__restrict__ count, FS32 p,
+                                                      const int32_t *__restrict__ count, P p,
                                                       const float *__restrict__ rho, float *__restrict__ f,
                                                       float *__restrict__ e_atom, double *__restrict__ part)
 {
@@ -281,23 +362,14 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
                 float dx, dy, dz;
                 disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
                 const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                const bool valid = t0 + u * TPA < cnt;
-                const bool in_d = valid && r2 < p.d2u, in_c = valid && r2 < p.c2u;
-                const float ru = __builtin_amdgcn_sqrtf(r2);
-                const float r = ru * p.len;
-                const float dpsi = in_d ? (fpi + __uint_as_float(pj[u].w)) * 2.f * (r - p.d) : 0.f;
-                const float t = r - p.c;
-                const float poly = __builtin_fmaf(__builtin_fmaf(p.p2, t, p.p1), t, p.p0);
-                const float dpoly = __builtin_fmaf(2.f * p.p2, t, p.p1);
-                const float dV = in_c ? t * __builtin_fmaf(t, dpoly, 2.f * poly) : 0.f;
                 // -(dU/dr) / r in the displacement unit: F = g * (dx, dy, dz)
-                float g = -(dpsi + dV) * __builtin_amdgcn_rcpf(ru);
-                g = in_d || in_c ? g : 0.f;
+                const PairOut o = force_term(p, r2, t0 + u * TPA < cnt, fpi + __uint_as_float(pj[u].w));
+                const float g = o.g;
                 bx = __builtin_fmaf(g, dx, bx);
                 by = __builtin_fmaf(g, dy, by);
                 bz = __builtin_fmaf(g, dz, bz);
-                if (ENERGY && (in_d || in_c)) {
-                    if (in_c) e += double(t * t * poly);
+                if (ENERGY && o.in) {
+                    e += double(o.v);
                     w[0] += double(g * dx * dx); w[1] += double(g * dy * dy); w[2] += double(g * dz * dz);
                     w[3] += double(g * dx * dy); w[4] += double(g * dx * dz); w[5] += double(g * dy * dz);
                 }
@@ -429,31 +501,32 @@ int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *x
     return MD_OK;
 }
 
-template <int TPA, bool CUBIC, bool E, bool C>
-static void launch_eam(uint32_t gb, hipStream_t s, int64_t n, uint4 *q, const List &l, const FS32 &p, float *rho,
+template <class P, int TPA, bool CUBIC, bool E, bool C>
+static void launch_eam(uint32_t gb, hipStream_t s, int64_t n, uint4 *q, const List &l, const P &p, float *rho,
                        float *fprime, float *f, float *ea, double *part1, double *part2)
 {
-    hipLaunchKernelGGL((k_eam_rho<TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx,
+    hipLaunchKernelGGL((k_eam_rho<P, TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx,
                        l.cnt, p, rho, fprime, part1);
-    hipLaunchKernelGGL((k_eam_force<TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx,
-                       l.cnt, p, rho, f, ea, part2);
+    hipLaunchKernelGGL((k_eam_force<P, TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap,
+                       l.idx, l.cnt, p, rho, f, ea, part2);
 }
 
-template <int TPA, bool CUBIC>
+template <class P, int TPA, bool CUBIC>
 static void dispatch_eam(bool e, bool c, uint32_t gb, hipStream_t s, int64_t n, uint4 *q, const List &l,
-                         const FS32 &p, float *rho, float *fprime, float *f, float *ea, double *p1, double *p2)
+                         const P &p, float *rho, float *fprime, float *f, float *ea, double *p1, double *p2)
 {
-    if (e && c) launch_eam<TPA, CUBIC, true, true>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
-    else if (e) launch_eam<TPA, CUBIC, true, false>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
-    else if (c) launch_eam<TPA, CUBIC, false, true>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
-    else launch_eam<TPA, CUBIC, false, false>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
+    if (e && c) launch_eam<P, TPA, CUBIC, true, true>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
+    else if (e) launch_eam<P, TPA, CUBIC, true, false>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
+    else if (c) launch_eam<P, TPA, CUBIC, false, true>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
+    else launch_eam<P, TPA, CUBIC, false, false>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
 }
 
-int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
-               const md_fs_t *fs, float *rho, float *fprime, float *f, float *e_atom, double *ev, int32_t flags,
-               void *ws, const WsLayout &w, hipStream_t s, Gate gate)
+// Both passes of an embedded-atom form P (geometry fields set here).
+template <class P>
+static int forces_two_pass(const md_box_t *box, int64_t n, uint32_t *xs, const List &l, P p, float *rho,
+                           float *fprime, float *f, float *e_atom, double *ev, int32_t flags, void *ws,
+                           const WsLayout &w, hipStream_t s)
 {
-    const List l{cap, idx, cnt};
     const bool energy = flags & MD_ENERGY;
     const bool comp = !(flags & MD_NO_COMPENSATE);
     double *part1 = ws_ptr<double>(ws, w.red1);
@@ -461,8 +534,25 @@ int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const 
     const bool cubic = is_cubic(box);
     const uint32_t gb = n > 0 ? blocks_for(n, kTPA) : 0;
     if (int64_t(gb) > w.red_blocks) return MD_ERR_WORKSPACE;
+    uint4 *q = reinterpret_cast<uint4 *>(xs);
+    if (n > 0) {
+        if (cubic) dispatch_eam<P, kTPA, true>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, e_atom, part1, part2);
+        else dispatch_eam<P, kTPA, false>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, e_atom, part1, part2);
+        MD_HIP_TRY(hipGetLastError());
+    }
+    if (energy) return launch_reduce_partials(part1, gb, part2, gb, ev, kReduceEAM, 0.0, 0.0, s);
+    return MD_OK;
+}
+
+// displacement unit of the FP32 pair kernels: L/2^32 in a cubic box, else 1
+static double disp_unit(const md_box_t *box) { return is_cubic(box) ? box->L[0] / 4294967296.0 : 1.0; }
+
+int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
+               const md_fs_t *fs, float *rho, float *fprime, float *f, float *e_atom, double *ev, int32_t flags,
+               void *ws, const WsLayout &w, hipStream_t s, Gate gate)
+{
     const double two32 = 4294967296.0;
-    const double u = cubic ? box->L[0] / two32 : 1.0;
+    const double u = disp_unit(box);
     FS32 p;
     p.ax = float(box->L[0] / two32);
     p.ay = float(box->L[1] / two32);
@@ -477,14 +567,33 @@ int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const 
     p.p2 = float(fs->c2);
     p.A = float(fs->A);
     p.gate = gate;
-    uint4 *q = reinterpret_cast<uint4 *>(xs);
-    if (n > 0) {
-        if (cubic) dispatch_eam<kTPA, true>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, e_atom, part1, part2);
-        else dispatch_eam<kTPA, false>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, e_atom, part1, part2);
-        MD_HIP_TRY(hipGetLastError());
-    }
-    if (energy) return launch_reduce_partials(part1, gb, part2, gb, ev, kReduceEAM, 0.0, 0.0, s);
-    return MD_OK;
+    return forces_two_pass(box, n, xs, List{cap, idx, cnt}, p, rho, fprime, f, e_atom, ev, flags, ws, w, s);
+}
+
+int forces_tb(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
+              const md_tb_t *tb, float *rho, float *fprime, float *f, float *e_atom, double *ev, int32_t flags,
+              void *ws, const WsLayout &w, hipStream_t s, Gate gate)
+{
+    const double two32 = 4294967296.0, log2e = 1.4426950408889634;
+    const double u = disp_unit(box);
+    TB32 p;
+    p.ax = float(box->L[0] / two32);
+    p.ay = float(box->L[1] / two32);
+    p.az = float(box->L[2] / two32);
+    p.len = float(u);
+    p.cut2u = float(tb->rc * tb->rc / (u * u));
+    p.rs = float(tb->rs);
+    p.iw = float(1.0 / (tb->rc - tb->rs));
+    const double kq = 2.0 * tb->q * log2e / tb->r0, kp = tb->p * log2e / tb->r0;
+    p.kq = float(kq);
+    p.cq = float(kq * tb->r0 + std::log2(tb->xi * tb->xi));
+    p.lq = float(2.0 * tb->q / tb->r0);
+    p.kp = float(kp);
+    p.cp = float(kp * tb->r0 + std::log2(2.0 * tb->A));
+    p.lp = float(tb->p / tb->r0);
+    p.A = 1.f;
+    p.gate = gate;
+    return forces_two_pass(box, n, xs, List{cap, idx, cnt}, p, rho, fprime, f, e_atom, ev, flags, ws, w, s);
 }
 
 }  // namespace md

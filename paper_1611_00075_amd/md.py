@@ -43,6 +43,16 @@ class FS(C.Structure):
                 ("c0", C.c_double), ("c1", C.c_double), ("c2", C.c_double)]
 
 
+class TB(C.Structure):
+    """md_tb_t: second-moment tight-binding parameters."""
+    _fields_ = [("A", C.c_double), ("xi", C.c_double), ("p", C.c_double), ("q", C.c_double),
+                ("r0", C.c_double), ("rs", C.c_double), ("rc", C.c_double)]
+
+
+def tb_params(tb: dict) -> TB:
+    return TB(*[float(tb[k]) for k in ("A", "xi", "p", "q", "r0", "rs", "rc")])
+
+
 MD_MLP_IN, MD_MLP_HID, MD_MLP_NPARAM = 16, 64, 5313
 
 
@@ -79,10 +89,10 @@ class System(C.Structure):
                 ("need_build", C.c_int32), ("phase", C.c_int32), ("timing", C.c_int32), ("pad_", C.c_int32),
                 ("force_ms", C.c_double), ("force_calls", C.c_int64),
                 ("mlp", MLP), ("mlp_w", C.c_void_p), ("dEdG", C.c_void_p), ("idx_in", C.c_void_p),
-                ("cnt_in", C.c_void_p)]
+                ("cnt_in", C.c_void_p), ("tb", TB)]
 
 
-MD_POT_LJ, MD_POT_EAM, MD_POT_MLP = 0, 1, 2
+MD_POT_LJ, MD_POT_EAM, MD_POT_MLP, MD_POT_TB = 0, 1, 2, 3
 
 
 class MDError(RuntimeError):
@@ -118,6 +128,8 @@ def lib():
                                    _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
         L.md_forces_eam.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(FS), _vp,
                                     _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_forces_tb.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(TB), _vp,
+                                   _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
         L.md_mlp_descriptors.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(MLP),
                                          _vp, _vp]
         L.md_mlp_eval.argtypes = [C.c_int64, _vp, C.POINTER(MLP), _vp, _vp, _vp, _vp]
@@ -273,6 +285,19 @@ def md_forces_eam(L, n: int, xs, row_cap: int, idx, count, fs: dict, rho, fprime
                                _ptr(e_atom, torch.float32, n, "e_atom"),
                                _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
                                _stream(stream)), "md_forces_eam")
+
+
+def md_forces_tb(L, n: int, xs, row_cap: int, idx, count, tb: dict, rho, fprime, f, ev, flags: int, ws,
+                 stream=None, e_atom=None):
+    import torch
+    p = tb_params(tb)
+    _check(lib().md_forces_tb(C.byref(box(L)), int(n), _ptr(xs, torch.int32, 4 * n, "xs"), int(row_cap),
+                              _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"),
+                              _ptr(count, torch.int32, n, "count"), C.byref(p), _ptr(rho, torch.float32, n, "rho"),
+                              _ptr(fprime, torch.float32, n, "fprime"), _ptr(f, torch.float32, 3 * n, "f"),
+                              _ptr(e_atom, torch.float32, n, "e_atom"),
+                              _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
+                              _stream(stream)), "md_forces_tb")
 
 
 def md_mlp_descriptors(L, n: int, xs, row_cap: int, idx, count, mlp: MLP, G, stream=None):

@@ -23,14 +23,15 @@ from . import md as M
 class Simulation:
     """One periodic system on one GPU.
 
-    potential: "lj" (params eps, sigma, rc), "eam" (Finnis-Sinclair dict) or
+    potential: "lj" (params eps, sigma, rc), "eam" (Finnis-Sinclair dict),
+    "tb" (second-moment tight-binding dict: A, xi, p, q, r0, rs, rc) or
     "mlp" (descriptor geometry and normalisation `mlp`, an md.MLP, and the
     MD_MLP_NPARAM bfloat16 parameters `mlp_w`, an int16 device tensor).
     Positions and velocities are FP64; forces FP32 (FP64 with pair_fp64).
     Atoms are kept in cell (Morton) order; `ids` maps back to input order.
     """
 
-    def __init__(self, L, x, v, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None, mlp=None, mlp_w=None,
+    def __init__(self, L, x, v, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None, tb=None, mlp=None, mlp_w=None,
                  skin=0.3, dt=0.005, mass=1.0, force_to_accel=1.0, reach=1, pair_fp64=False,
                  compensate=True, device="cuda", row_cap=None, list_slack=1.2):
         self.L = np.asarray(L, dtype=np.float64).reshape(3)
@@ -39,11 +40,14 @@ class Simulation:
         self.potential = potential
         self.lj = tuple(float(a) for a in lj)
         self.fs = fs
+        self.tb = tb
         self.mlp, self.mlp_w = mlp, mlp_w
         if potential == "lj":
             rc = self.lj[2]
         elif potential == "eam":
             rc = max(fs["d"], fs["c"])
+        elif potential == "tb":
+            rc = float(tb["rc"])
         elif potential == "mlp":
             if mlp is None or mlp_w is None:
                 raise ValueError("potential 'mlp' needs mlp and mlp_w")
@@ -60,7 +64,7 @@ class Simulation:
         if not compensate:
             self.flags |= M.MD_NO_COMPENSATE
         if potential != "lj" and pair_fp64:
-            raise ValueError("the EAM and MLP paths are FP32 only")
+            raise ValueError("the embedded-atom and MLP paths are FP32 only")
         self.dev = torch.device(device)
         self.list_slack = float(list_slack)
         d = self.dev
@@ -158,6 +162,9 @@ class Simulation:
         elif self.potential == "eam":
             M.md_forces_eam(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.fs, self.rho,
                             self.fprime, self.f, self.ev, fl, self.ws, e_atom=ea)
+        elif self.potential == "tb":
+            M.md_forces_tb(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.tb, self.rho,
+                           self.fprime, self.f, self.ev, fl, self.ws, e_atom=ea)
         else:
             M.md_forces_mlp(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.mlp, self.mlp_w,
                             self.dEdG, self.idx_in, self.cnt_in, ea, self.f, self.ev, fl, self.ws)
@@ -235,7 +242,10 @@ class Simulation:
         S.status, S.host_status = ptr(self.status), ptr(self._flag_host)
         S.ws, S.ws_bytes = ptr(self.ws), self.ws.numel()
         S.row_cap = self.row_cap
-        S.potential = {"lj": M.MD_POT_LJ, "eam": M.MD_POT_EAM, "mlp": M.MD_POT_MLP}[self.potential]
+        if self.tb is not None:
+            S.tb = M.tb_params(self.tb)
+        S.potential = {"lj": M.MD_POT_LJ, "eam": M.MD_POT_EAM, "mlp": M.MD_POT_MLP,
+                       "tb": M.MD_POT_TB}[self.potential]
         if self.potential == "mlp":
             S.mlp, S.mlp_w, S.dEdG = self.mlp, ptr(self.mlp_w), ptr(self.dEdG)
             S.idx_in, S.cnt_in = ptr(self.idx_in), ptr(self.cnt_in)
