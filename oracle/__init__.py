@@ -79,6 +79,8 @@ def _declare(L):
                                 C.POINTER(FSParams), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_forces_tb.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
                                C.POINTER(TBParams), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_forces_tbm.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i32p, _i64p, _i32p,
+                                C.POINTER(TBParams), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_md_run.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                             C.POINTER(MDParams), C.c_int64, _dp, _dp, _dp]
     L.or_md_run.restype = C.c_int64
@@ -191,6 +193,22 @@ def forces_tb(x, L, off, idx, tb: dict):
                        _p(np.ascontiguousarray(off, np.int64), _i64p),
                        _p(np.ascontiguousarray(idx, np.int32), _i32p), C.byref(prm),
                        _p(rho), _p(fp), *[_p(c) for c in f], _p(ea), _p(ev))
+    return dict(rho=rho, fprime=fp, f=np.stack(f, axis=1), e_atom=ea, ev=ev)
+
+
+def forces_tbm(x, L, off, idx, types, pairs):
+    """FP64 two-element tight-binding potential; `pairs` = three parameter
+    dicts for the element pairs 0-0, 0-1, 1-1.  Output as forces_eam."""
+    xs = _soa(x)
+    n = len(xs[0])
+    f = [np.zeros(n) for _ in range(3)]
+    rho, fp, ea, ev = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(8)
+    prm = (TBParams * 3)(*[TBParams(*[float(t[k]) for k in ("A", "xi", "p", "q", "r0", "rs", "rc")])
+                           for t in pairs])
+    lib().or_forces_tbm(n, _p(_box(L)), *[_p(c) for c in xs], _p(np.ascontiguousarray(types, np.int32), _i32p),
+                        _p(np.ascontiguousarray(off, np.int64), _i64p),
+                        _p(np.ascontiguousarray(idx, np.int32), _i32p), prm,
+                        _p(rho), _p(fp), *[_p(c) for c in f], _p(ea), _p(ev))
     return dict(rho=rho, fprime=fp, f=np.stack(f, axis=1), e_atom=ea, ev=ev)
 
 

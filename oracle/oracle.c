@@ -397,6 +397,77 @@ void or_forces_tb(int64_t n, const double L[3], const double *x,
     for (int a = 0; a < 6; ++a) ev[2 + a] = W[a];
 }
 
+void or_forces_tbm(int64_t n, const double L[3], const double *x,
+                   const double *y, const double *z, const int32_t *types,
+                   const int64_t *offsets, const int32_t *idx,
+                   const or_tb_t pair[3], double *rho, double *fprime,
+                   double *fx, double *fy, double *fz, double *e_atom,
+                   double ev[8])
+{
+    double d[3];
+    /* step 1: rho_i = sum_{j != i} psi_{t_i t_j}(r_ij) */
+    for (int64_t i = 0; i < n; ++i) rho[i] = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            int64_t j = idx[k];
+            if (j <= i) continue;
+            const or_tb_t *p = &pair[types[i] + types[j]];
+            double r2 = dist2(L, x, y, z, i, j, d);
+            if (!(r2 < p->rc * p->rc)) continue;
+            double r = sqrt(r2), S, dS;
+            tb_switch(p, r, &S, &dS);
+            double psi = p->xi * p->xi * exp(-2.0 * p->q * (r / p->r0 - 1.0)) * S;
+            rho[i] += psi;
+            rho[j] += psi;
+        }
+    /* step 2: embedding F_i = -sqrt(rho_i) and F'_i */
+    double Eemb = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double F = 0.0, Fp = 0.0;
+        if (rho[i] > 0.0) {
+            double s = sqrt(rho[i]);
+            F = -s;
+            Fp = -1.0 / (2.0 * s);
+        }
+        fprime[i] = Fp;
+        Eemb += F;
+        if (e_atom) e_atom[i] = F;
+        fx[i] = fy[i] = fz[i] = 0.0;
+    }
+    /* step 3: pair interaction and forces */
+    double Epair = 0.0, W[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            int64_t j = idx[k];
+            if (j <= i) continue;
+            const or_tb_t *p = &pair[types[i] + types[j]];
+            double r2 = dist2(L, x, y, z, i, j, d);
+            if (!(r2 < p->rc * p->rc)) continue;
+            double r = sqrt(r2), S, dS;
+            tb_switch(p, r, &S, &dS);
+            double eq = p->xi * p->xi * exp(-2.0 * p->q * (r / p->r0 - 1.0));
+            double ep = 2.0 * p->A * exp(-p->p * (r / p->r0 - 1.0));
+            double dpsi = eq * (dS - 2.0 * p->q / p->r0 * S);
+            double Phi = ep * S, dPhi = ep * (dS - p->p / p->r0 * S);
+            double dUdr = (fprime[i] + fprime[j]) * dpsi + dPhi;
+            Epair += Phi;
+            if (e_atom) {
+                e_atom[i] += 0.5 * Phi;
+                e_atom[j] += 0.5 * Phi;
+            }
+            double R[3] = {-d[0], -d[1], -d[2]};
+            double g = -dUdr / r; /* F_i = g R */
+            fx[i] += g * R[0]; fy[i] += g * R[1]; fz[i] += g * R[2];
+            fx[j] -= g * R[0]; fy[j] -= g * R[1]; fz[j] -= g * R[2];
+            W[0] += g * R[0] * R[0]; W[1] += g * R[1] * R[1];
+            W[2] += g * R[2] * R[2]; W[3] += g * R[0] * R[1];
+            W[4] += g * R[0] * R[2]; W[5] += g * R[1] * R[2];
+        }
+    ev[0] = Eemb + Epair;
+    ev[1] = Eemb;
+    for (int a = 0; a < 6; ++a) ev[2 + a] = W[a];
+}
+
 /* ------------------------------------------------------------------ */
 /* velocity Verlet with the displacement rebuild rule                  */
 /* ------------------------------------------------------------------ */

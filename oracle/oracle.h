@@ -123,6 +123,16 @@ void or_forces_tb(int64_t n, const double L[3], const double *x,
                   double *fprime, double *fx, double *fy, double *fz,
                   double *e_atom, double ev[8]);
 
+/* Two elements (types[i] = 0 or 1): the same form with the parameters of
+ * the pair's kind, pair[types[i] + types[j]] (0: 0-0, 1: 0-1, 2: 1-1);
+ * F(rho) = -sqrt(rho) for both elements.  Outputs as or_forces_tb. */
+void or_forces_tbm(int64_t n, const double L[3], const double *x,
+                   const double *y, const double *z, const int32_t *types,
+                   const int64_t *offsets, const int32_t *idx,
+                   const or_tb_t pair[3], double *rho, double *fprime,
+                   double *fx, double *fy, double *fz, double *e_atom,
+                   double ev[8]);
+
 /* ---- velocity-Verlet molecular dynamics (Sec. 3.3) ---- */
 
 enum { OR_POT_LJ = 0, OR_POT_EAM = 1 };

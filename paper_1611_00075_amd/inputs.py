@@ -43,6 +43,19 @@ FS_CU = dict(A=0.6904081156, d=4.4, c=3.25,
 # from the cohesive energy 3.54 eV and zero pressure at a = 3.615 A.
 TB_CU = dict(A=0.1044093115, xi=1.3137843239, p=10.0, q=2.5, r0=2.5561910140, rs=4.5, rc=5.0)
 
+# Two elements of the same form (a Cu-like 0 and an Au-like 1; synthetic):
+# a common smooth cutoff 5.2-5.7 A (Cu shells 1-4 inside, Au shells 1-3),
+# A and xi of each element solved from its cohesive energy (3.54 eV at
+# a = 3.615 A; 3.81 eV at a = 4.078 A) and zero pressure; the mixed pair by
+# geometric means of A and xi and arithmetic means of p, q and r0.
+TB2_CU = dict(A=0.1051590565, xi=1.3123219176, p=10.0, q=2.5, r0=2.5561910140, rs=5.2, rc=5.7)
+TB2_AU = dict(A=0.1313829015, xi=1.5090414023, p=10.5, q=3.0, r0=2.8835814537, rs=5.2, rc=5.7)
+TB2_CUAU = dict(A=float(np.sqrt(TB2_CU["A"] * TB2_AU["A"])), xi=float(np.sqrt(TB2_CU["xi"] * TB2_AU["xi"])),
+                p=0.5 * (TB2_CU["p"] + TB2_AU["p"]), q=0.5 * (TB2_CU["q"] + TB2_AU["q"]),
+                r0=0.5 * (TB2_CU["r0"] + TB2_AU["r0"]), rs=5.2, rc=5.7)
+TB2_PAIRS = (TB2_CU, TB2_CUAU, TB2_AU)
+AU_A0 = 4.078
+
 FCC_BASIS = np.array([[0.0, 0.0, 0.0],
                       [0.5, 0.5, 0.0],
                       [0.5, 0.0, 0.5],
