@@ -54,6 +54,7 @@ const char *md_error_string(int status);
 #define MD_PAIR_FP64     0x2  /* forces: FP64 pair arithmetic, FP64 forces */
 #define MD_NO_COMPENSATE 0x4  /* forces: plain FP32 accumulation (timing aid) */
 #define MD_MLP_REUSE     0x8  /* md_forces_mlp: dEdG already holds dE_i/dG_i */
+#define MD_XS_ELEMENT    0x10 /* md_integrate: keep bit 0 of xs[4i+3] (the element) */
 
 /* ---- geometry ---- */
 
@@ -233,6 +234,28 @@ int md_forces_tb(const md_box_t *box, int64_t n, uint32_t *xs,
                  float *e_atom, double *ev, int32_t flags, void *ws,
                  size_t ws_bytes, void *stream);
 
+/* Two elements (the Cu-Au systems of Sec. 3.1): the same form with the
+ * parameters of each pair's kind, pair[t_i + t_j] (0: 0-0, 1: 0-1, 2: 1-1),
+ * F(rho) = -sqrt(rho) for both.  The element t_i (0 or 1) of atom i travels
+ * as bit 0 of xs[4i+3]: on entry that word must hold the element
+ * (md_set_elements; md_integrate with MD_XS_ELEMENT keeps it); on return it
+ * holds F'_i with its lowest mantissa bit replaced by the element.
+ * Otherwise as md_forces_tb. */
+typedef struct md_tbm {
+    md_tb_t pair[3];
+} md_tbm_t;
+
+int md_forces_tbm(const md_box_t *box, int64_t n, uint32_t *xs,
+                  int32_t row_cap, const int32_t *idx, const int32_t *count,
+                  const md_tbm_t *tbm, float *rho, float *fprime, float *f,
+                  float *e_atom, double *ev, int32_t flags, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* xs[4i+3] = types[i] & 1 for i < n (the element word md_forces_tbm reads;
+ * xs from md_scale_positions). */
+int md_set_elements(int64_t n, const int32_t *types, uint32_t *xs,
+                    void *stream);
+
 /* ---- steps a8/a9: learned descriptor-MLP potential ----
  *
  * A learned stand-in for the embedded-atom energy of Eqs. (1)-(2): like
@@ -364,7 +387,8 @@ int md_mlp_train_step(int64_t batch, const int32_t *sel, const float *G,
  *   rebuild rule: moved more than half the skin since the last build);
  *   status[1] gets bit 0 set when a new position is not finite.  status is
  *   never cleared by the library.  If xs is not NULL, the scaled
- *   coordinates are rewritten from the new positions (xs[4i+3] set to 0).
+ *   coordinates are rewritten from the new positions (xs[4i+3] set to 0,
+ *   or to its own bit 0 with MD_XS_ELEMENT in flags).
  * MD_KICK: if ke is not NULL, *ke (device) = 1/2 mass sum |v|^2 over the
  *   updated velocities, reduced in FP64 in a fixed order. */
 int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x,
@@ -379,6 +403,7 @@ int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x,
 #define MD_POT_EAM 1
 #define MD_POT_MLP 2
 #define MD_POT_TB  3
+#define MD_POT_TBM 4
 
 /* One system for md_run.  The caller fills every field (device buffers are
  * caller-owned; sizes as for the calls above) and keeps the struct between
@@ -408,7 +433,7 @@ typedef struct md_system {
     size_t ws_bytes;
     int32_t row_cap;
     int32_t row_cap_needed;     /* out: set with MD_ERR_CAPACITY */
-    int32_t potential;          /* MD_POT_LJ, MD_POT_EAM, MD_POT_MLP or MD_POT_TB */
+    int32_t potential;          /* MD_POT_LJ, MD_POT_EAM, MD_POT_MLP, MD_POT_TB or MD_POT_TBM */
     int32_t flags;              /* MD_PAIR_FP64 (LJ only), MD_NO_COMPENSATE */
     int32_t need_build;         /* 1: build lists (and forces) before stepping */
     int32_t phase;              /* 0: at a step boundary; 1: a step is in flight */
@@ -421,13 +446,15 @@ typedef struct md_system {
     float *dEdG;                /* MD_POT_MLP: [16n] scratch */
     int32_t *idx_in, *cnt_in;   /* MD_POT_MLP: compact list scratch, sized as idx, count */
     md_tb_t tb;                 /* MD_POT_TB (rho, fprime as for MD_POT_EAM) */
+    md_tbm_t tbm;               /* MD_POT_TBM (rho, fprime as for MD_POT_EAM) */
+    int32_t *types, *types_scratch;   /* MD_POT_TBM: [n] element of each sorted atom, permuted at builds */
 } md_system_t;
 
 /* Runs `steps` velocity-Verlet steps (Sec. 3.3) of the path: kick + drift
  * with the rebuild check, md_bin_cells + md_permute + md_scale_positions +
  * md_build_neighbors whenever some atom moved more than skin/2 since the
- * last build, forces (md_forces_lj, md_forces_eam, md_forces_mlp or
- * md_forces_tb), kick.  Between two
+ * last build, forces (md_forces_lj, md_forces_eam, md_forces_mlp,
+ * md_forces_tb or md_forces_tbm), kick.  Between two
  * steps the closing half kick and the next opening half kick are applied as
  * one kick with the same forces.  On entry with need_build set (a new
  * system) the lists and forces are built first; otherwise f must hold the

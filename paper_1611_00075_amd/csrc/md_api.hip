@@ -278,6 +278,29 @@ int md_forces_tb(const md_box_t *box, int64_t n, uint32_t *xs, int32_t row_cap, 
                      as_stream(stream));
 }
 
+int md_forces_tbm(const md_box_t *box, int64_t n, uint32_t *xs, int32_t row_cap, const int32_t *idx,
+                  const int32_t *count, const md_tbm_t *tbm, float *rho, float *fprime, float *f, float *e_atom,
+                  double *ev, int32_t flags, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!box_ok(box)) return MD_ERR_BOX;
+    if (!tbm || !tb_ok(&tbm->pair[0]) || !tb_ok(&tbm->pair[1]) || !tb_ok(&tbm->pair[2])) return MD_ERR_ARG;
+    if (n < 0 || n > kMaxAtomsXs || row_cap < 1 || row_cap % 8 || row_cap > MD_MAX_ROW_CAP) return MD_ERR_ARG;
+    if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE)) return MD_ERR_ARG;
+    if (n > 0 && (!xs || !idx || !count || !rho || !fprime || !f)) return MD_ERR_ARG;
+    if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
+    if (e_atom && !(flags & MD_ENERGY)) return MD_ERR_ARG;
+    WsLayout w;
+    if (int rc = ws_check_n(n, ws, ws_bytes, w)) return rc;
+    return forces_tbm(box, n, xs, row_cap, idx, count, tbm, rho, fprime, f, e_atom, ev, flags, ws, w,
+                      as_stream(stream));
+}
+
+int md_set_elements(int64_t n, const int32_t *types, uint32_t *xs, void *stream)
+{
+    if (n < 0 || n > kMaxAtomsXs || (n > 0 && (!types || !xs))) return MD_ERR_ARG;
+    return set_elements(n, types, xs, as_stream(stream));
+}
+
 int md_mlp_descriptors(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t row_cap, const int32_t *idx,
                        const int32_t *count, const md_mlp_t *mlp, float *G, void *stream)
 {
@@ -356,7 +379,8 @@ int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x, doubl
                  uint32_t *xs, double *ke, int32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
     if (!box_ok(box)) return MD_ERR_BOX;
-    if (n < 0 || n > kMaxAtoms || (flags & ~MD_PAIR_FP64)) return MD_ERR_ARG;
+    if (n < 0 || n > kMaxAtoms || (flags & ~(MD_PAIR_FP64 | MD_XS_ELEMENT))) return MD_ERR_ARG;
+    if ((flags & MD_XS_ELEMENT) && (flags & MD_PAIR_FP64)) return MD_ERR_ARG;
     if (phase != MD_KICK_DRIFT && phase != MD_KICK) return MD_ERR_ARG;
     if (n > 0 && (!v || !f)) return MD_ERR_ARG;
     if (phase == MD_KICK_DRIFT && n > 0 && (!x || !status)) return MD_ERR_ARG;
@@ -373,9 +397,12 @@ int md_run(md_system_t *sys, int64_t steps, void *stream)
     if (!sys || steps < 0 || !box_ok(&sys->box) || !grid_ok(&sys->grid) || sys->n < 0 || sys->n > kMaxAtoms)
         return MD_ERR_ARG;
     if (sys->potential != MD_POT_LJ && sys->potential != MD_POT_EAM && sys->potential != MD_POT_MLP &&
-        sys->potential != MD_POT_TB)
+        sys->potential != MD_POT_TB && sys->potential != MD_POT_TBM)
         return MD_ERR_ARG;
     if (sys->potential == MD_POT_TB && !tb_ok(&sys->tb)) return MD_ERR_ARG;
+    if (sys->potential == MD_POT_TBM &&
+        (!tb_ok(&sys->tbm.pair[0]) || !tb_ok(&sys->tbm.pair[1]) || !tb_ok(&sys->tbm.pair[2])))
+        return MD_ERR_ARG;
     if (sys->flags & ~(MD_PAIR_FP64 | MD_NO_COMPENSATE)) return MD_ERR_ARG;
     if (sys->potential != MD_POT_LJ && (sys->flags & MD_PAIR_FP64)) return MD_ERR_ARG;
     if (sys->potential == MD_POT_MLP && !mlp_ok(&sys->mlp)) return MD_ERR_ARG;
@@ -391,8 +418,10 @@ int md_run(md_system_t *sys, int64_t steps, void *stream)
             !sys->status)
             return MD_ERR_ARG;
         if (!f64 && !sys->xs) return MD_ERR_ARG;
-        if ((sys->potential == MD_POT_EAM || sys->potential == MD_POT_TB) && (!sys->rho || !sys->fprime))
+        if ((sys->potential == MD_POT_EAM || sys->potential == MD_POT_TB || sys->potential == MD_POT_TBM) &&
+            (!sys->rho || !sys->fprime))
             return MD_ERR_ARG;
+        if (sys->potential == MD_POT_TBM && (!sys->types || !sys->types_scratch)) return MD_ERR_ARG;
         if (sys->potential == MD_POT_MLP && (!sys->mlp_w || !sys->dEdG || !sys->idx_in || !sys->cnt_in))
             return MD_ERR_ARG;
     }

@@ -187,6 +187,23 @@ int scale_positions(const md_box_t *box, int64_t n, const double *x, uint32_t *x
     return MD_OK;
 }
 
+// The element of each atom (0 or 1; only bit 0 is used) into the fourth word
+// of its scaled coordinates.
+__global__ __launch_bounds__(kBlock) void k_set_elements(int64_t n, const int32_t *types, uint4 *xs)
+{
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n) xs[i].w = uint32_t(types[i]) & 1u;
+}
+
+int set_elements(int64_t n, const int32_t *types, uint32_t *xs, hipStream_t s)
+{
+    if (n <= 0) return MD_OK;
+    const uint32_t gb = uint32_t((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_set_elements, dim3(gb), dim3(kBlock), 0, s, n, types, reinterpret_cast<uint4 *>(xs));
+    MD_HIP_TRY(hipGetLastError());
+    return MD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // neighbour lists
 // ---------------------------------------------------------------------------

@@ -155,6 +155,10 @@ int forces_eam(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, 
 int forces_tb(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, const int32_t *, const md_tb_t *,
               float *, float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t,
               Gate = {});
+int forces_tbm(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, const int32_t *, const md_tbm_t *,
+               float *, float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t,
+               Gate = {});
+int set_elements(int64_t, const int32_t *, uint32_t *, hipStream_t);
 int integrate(int32_t, const md_box_t *, int64_t, double *, double *, const void *, double, double, double,
               const double *, double, int32_t *, int32_t, uint32_t *, double *, int32_t, void *, const WsLayout &,
               hipStream_t);
@@ -172,6 +176,7 @@ int mlp_grad_update(int64_t, const int32_t *, const float *, const float *, cons
                     float *, double *, const md_adam_t *, float *, float *, float *, uint16_t *, void *, hipStream_t);
 int run(md_system_t *sys, int64_t steps, hipStream_t s);
 int kick_drift(const md_box_t *box, int64_t n, double *x, double *v, const void *f, bool f64, double kick, double dt,
-               const double *xref, double half_skin_sq, int32_t *status, int32_t tag, uint32_t *xs, hipStream_t s);
+               const double *xref, double half_skin_sq, int32_t *status, int32_t tag, uint32_t *xs, hipStream_t s,
+               bool keep_element = false);
 
 }  // namespace md

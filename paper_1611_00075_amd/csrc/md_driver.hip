@@ -95,6 +95,12 @@ int rebuild(md_system_t *sys, const WsLayout &w, hipStream_t s, int32_t *host_de
         if ((rc = permute(n, 1, sys->perm, sys->ids_scratch, sys->ids, 4, s))) return rc;
         MD_HIP_TRY(hipMemcpyAsync(sys->xref, sys->x, b3, hipMemcpyDeviceToDevice, s));
         if (!(sys->flags & MD_PAIR_FP64) && (rc = scale_positions(&sys->box, n, sys->x, sys->xs, s))) return rc;
+        if (sys->potential == MD_POT_TBM) {
+            // elements follow their atoms into the new order and into the scaled coordinates
+            MD_HIP_TRY(hipMemcpyAsync(sys->types_scratch, sys->types, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+            if ((rc = permute(n, 1, sys->perm, sys->types_scratch, sys->types, 4, s))) return rc;
+            if ((rc = set_elements(n, sys->types, sys->xs, s))) return rc;
+        }
     }
     rc = build_neighbors(&sys->grid, n, sys->x, sys->cell_start, sys->row_cap, sys->idx, sys->count, sys->max_count,
                          nullptr, sys->ws, w, s);
@@ -144,6 +150,10 @@ int forces(md_system_t *sys, const WsLayout &w, hipStream_t s, Gate gate = {})
     if (sys->potential == MD_POT_LJ)
         return forces_lj(&sys->box, sys->n, sys->x, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->lj, sys->f,
                          nullptr, sys->flags & (MD_PAIR_FP64 | MD_NO_COMPENSATE), sys->ws, w, s, gate);
+    if (sys->potential == MD_POT_TBM)
+        return forces_tbm(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->tbm, sys->rho,
+                          sys->fprime, static_cast<float *>(sys->f), nullptr, nullptr, sys->flags & MD_NO_COMPENSATE,
+                          sys->ws, w, s, gate);
     if (sys->potential == MD_POT_TB)
         return forces_tb(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->tb, sys->rho,
                          sys->fprime, static_cast<float *>(sys->f), nullptr, nullptr, sys->flags & MD_NO_COMPENSATE,
@@ -254,7 +264,7 @@ int run(md_system_t *sys, int64_t steps, hipStream_t s)
     bool ready = false;   // forces of the in-flight step already queued
     const auto drift = [&](double h, int32_t tag) -> int {
         int r = kick_drift(&sys->box, sys->n, sys->x, sys->v, sys->f, f64, h, sys->dt, sys->xref, sys->half_skin_sq,
-                           sys->status, tag, xs, s);
+                           sys->status, tag, xs, s, sys->potential == MD_POT_TBM);
         if (r || (r = post_flag(sys, host_dev, tag, s))) return r;
         timer.start(s);
         if ((r = forces(sys, w, s, Gate{sys->status, tag}))) return r;

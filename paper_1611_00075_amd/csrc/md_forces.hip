@@ -194,6 +194,7 @@ struct FS32 {
     float d2u, c2u;         // d^2, c^2 in that unit
     float d, c, p0, p1, p2, A;  // physical
     Gate gate;
+    static constexpr int kRhoWords = 3;   // words of a neighbour's scaled coordinates pass 1 reads
 };
 
 // Second-moment tight-binding form: psi = exp2(cq - kq r) S(r),
@@ -208,26 +209,44 @@ struct TB32 {
     float kp, cp, lp;       // pair function, likewise
     float A;                // embedding prefactor (1)
     Gate gate;
+    static constexpr int kRhoWords = 3;
 };
 
-// ---- pair terms of the two forms ------------------------------------------
+// Two elements: the tight-binding constants per pair kind k = t_i + t_j
+// (0: 0-0, 1: 0-1, 2: 1-1).  The element of atom i is bit 0 of the fourth
+// word of its scaled coordinates (on entry the element itself; after pass 1
+// F'_i with its lowest mantissa bit replaced by the element).
+struct TBM32 {
+    float ax, ay, az;       // L_a / 2^32 (non-cubic boxes)
+    float len;              // length unit of the displacements (s or 1)
+    float cut2u[3], rs[3], iw[3];
+    float kq[3], cq[3], lq[3];
+    float kp[3], cp[3], lp[3];
+    float A;                // embedding prefactor (1)
+    Gate gate;
+    static constexpr int kRhoWords = 4;
+};
+
+// ---- pair terms of the forms ------------------------------------------------
 // rho_term: psi(r) of a listed pair (0 when not counted); force_term: the
 // force factor g = -(dU/dr)/r_u (F_i = g d, d in the displacement unit) and
-// the pair energy of the pair, given fsum = F'_i + F'_j.
+// the pair energy of the pair.  wi, wj: the fourth words of the two atoms'
+// scaled coordinates (F' after pass 1); fprime_word: the word pass 1 stores.
 
 struct PairOut {
     float g, v;
     bool in;
 };
 
-__device__ __forceinline__ float rho_term(const FS32 &p, float r2, bool valid)
+__device__ __forceinline__ float rho_term(const FS32 &p, float r2, bool valid, uint32_t, uint32_t)
 {
     const float t = __builtin_amdgcn_sqrtf(r2) * p.len - p.d;
     return (valid && r2 < p.d2u) ? t * t : 0.f;
 }
 
-__device__ __forceinline__ PairOut force_term(const FS32 &p, float r2, bool valid, float fsum)
+__device__ __forceinline__ PairOut force_term(const FS32 &p, float r2, bool valid, uint32_t wi, uint32_t wj)
 {
+    const float fsum = __uint_as_float(wi) + __uint_as_float(wj);
     const bool in_d = valid && r2 < p.d2u, in_c = valid && r2 < p.c2u;
     const float ru = __builtin_amdgcn_sqrtf(r2);
     const float r = ru * p.len;
@@ -241,37 +260,82 @@ __device__ __forceinline__ PairOut force_term(const FS32 &p, float r2, bool vali
     return {g, in_c ? t * t * poly : 0.f, in_d || in_c};
 }
 
+__device__ __forceinline__ uint32_t fprime_word(const FS32 &, float fp, uint32_t) { return __float_as_uint(fp); }
+
 // S(r) and dS/dr of the smooth cutoff, branch-free (x clamped to [0, 1])
-__device__ __forceinline__ void tb_switch(const TB32 &p, float r, float &S, float &dS)
+__device__ __forceinline__ void tb_switch(float r, float rs, float iw, float &S, float &dS)
 {
-    const float x = fminf(fmaxf((r - p.rs) * p.iw, 0.f), 1.f);
+    const float x = fminf(fmaxf((r - rs) * iw, 0.f), 1.f);
     const float x2 = x * x, y = 1.f - x;
     S = __builtin_fmaf(-x2 * x, __builtin_fmaf(__builtin_fmaf(6.f, x, -15.f), x, 10.f), 1.f);
-    dS = -30.f * p.iw * x2 * y * y;
+    dS = -30.f * iw * x2 * y * y;
 }
 
-__device__ __forceinline__ float rho_term(const TB32 &p, float r2, bool valid)
+// the tight-binding pair terms from one kind's constants
+__device__ __forceinline__ float tb_psi(float r, float rs, float iw, float kq, float cq)
 {
-    const float r = __builtin_amdgcn_sqrtf(r2) * p.len;
     float S, dS;
-    tb_switch(p, r, S, dS);
-    const float psi = __builtin_amdgcn_exp2f(__builtin_fmaf(-p.kq, r, p.cq)) * S;
+    tb_switch(r, rs, iw, S, dS);
+    return __builtin_amdgcn_exp2f(__builtin_fmaf(-kq, r, cq)) * S;
+}
+
+__device__ __forceinline__ float2 tb_force(float r, float ru, float fsum, float rs, float iw, float kq, float cq,
+                                          float lq, float kp, float cp, float lp)
+{
+    float S, dS;
+    tb_switch(r, rs, iw, S, dS);
+    const float eq = __builtin_amdgcn_exp2f(__builtin_fmaf(-kq, r, cq));
+    const float ep = __builtin_amdgcn_exp2f(__builtin_fmaf(-kp, r, cp));
+    const float dpsi = fsum * eq * __builtin_fmaf(-lq, S, dS);
+    const float dPhi = ep * __builtin_fmaf(-lp, S, dS);
+    return make_float2(-(dpsi + dPhi) * __builtin_amdgcn_rcpf(ru), ep * S);
+}
+
+__device__ __forceinline__ float rho_term(const TB32 &p, float r2, bool valid, uint32_t, uint32_t)
+{
+    const float psi = tb_psi(__builtin_amdgcn_sqrtf(r2) * p.len, p.rs, p.iw, p.kq, p.cq);
     return (valid && r2 < p.cut2u) ? psi : 0.f;
 }
 
-__device__ __forceinline__ PairOut force_term(const TB32 &p, float r2, bool valid, float fsum)
+__device__ __forceinline__ PairOut force_term(const TB32 &p, float r2, bool valid, uint32_t wi, uint32_t wj)
 {
     const bool in = valid && r2 < p.cut2u;
     const float ru = __builtin_amdgcn_sqrtf(r2);
-    const float r = ru * p.len;
-    float S, dS;
-    tb_switch(p, r, S, dS);
-    const float eq = __builtin_amdgcn_exp2f(__builtin_fmaf(-p.kq, r, p.cq));
-    const float ep = __builtin_amdgcn_exp2f(__builtin_fmaf(-p.kp, r, p.cp));
-    const float dpsi = fsum * eq * __builtin_fmaf(-p.lq, S, dS);
-    const float dPhi = ep * __builtin_fmaf(-p.lp, S, dS);
-    const float g = -(dpsi + dPhi) * __builtin_amdgcn_rcpf(ru);
-    return {in ? g : 0.f, in ? ep * S : 0.f, in};
+    const float2 o = tb_force(ru * p.len, ru, __uint_as_float(wi) + __uint_as_float(wj), p.rs, p.iw, p.kq, p.cq,
+                              p.lq, p.kp, p.cp, p.lp);
+    return {in ? o.x : 0.f, in ? o.y : 0.f, in};
+}
+
+__device__ __forceinline__ uint32_t fprime_word(const TB32 &, float fp, uint32_t) { return __float_as_uint(fp); }
+
+// per-lane choice among the three pair kinds (branch-free)
+__device__ __forceinline__ float sel3(const float (&v)[3], uint32_t k)
+{
+    return k == 0u ? v[0] : (k == 1u ? v[1] : v[2]);
+}
+
+__device__ __forceinline__ float rho_term(const TBM32 &p, float r2, bool valid, uint32_t wi, uint32_t wj)
+{
+    const uint32_t k = (wi & 1u) + (wj & 1u);
+    const float psi = tb_psi(__builtin_amdgcn_sqrtf(r2) * p.len, sel3(p.rs, k), sel3(p.iw, k), sel3(p.kq, k),
+                             sel3(p.cq, k));
+    return (valid && r2 < sel3(p.cut2u, k)) ? psi : 0.f;
+}
+
+__device__ __forceinline__ PairOut force_term(const TBM32 &p, float r2, bool valid, uint32_t wi, uint32_t wj)
+{
+    const uint32_t k = (wi & 1u) + (wj & 1u);
+    const bool in = valid && r2 < sel3(p.cut2u, k);
+    const float ru = __builtin_amdgcn_sqrtf(r2);
+    const float fsum = __uint_as_float(wi & ~1u) + __uint_as_float(wj & ~1u);
+    const float2 o = tb_force(ru * p.len, ru, fsum, sel3(p.rs, k), sel3(p.iw, k), sel3(p.kq, k), sel3(p.cq, k),
+                              sel3(p.lq, k), sel3(p.kp, k), sel3(p.cp, k), sel3(p.lp, k));
+    return {in ? o.x : 0.f, in ? o.y : 0.f, in};
+}
+
+__device__ __forceinline__ uint32_t fprime_word(const TBM32 &, float fp, uint32_t wi)
+{
+    return (__float_as_uint(fp) & ~1u) | (wi & 1u);
 }
 
 // pass 1: rho_i = sum psi(r_ij), then F_i = -A sqrt(rho_i), F'_i; F'_i is
@@ -292,17 +356,19 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
 
     const SliceBufs b = slice_bufs(xs, n, idx, cap, blk);
     float s = 0.f, c = 0.f;
+    uint32_t wi = 0;
     if (i < n) {
         const uint4 pi = xs[i];
+        wi = pi.w;
         const int32_t cnt = min(count[i], cap);
-        walk_buf<U, 3>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
+        walk_buf<U, P::kRhoWords>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
             float bs = 0.f;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 float dx, dy, dz;
                 disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
                 const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                bs += rho_term(p, r2, t0 + u * TPA < cnt);
+                bs += rho_term(p, r2, t0 + u * TPA < cnt, pi.w, pj[u].w);
             }
             acc_sum<COMP>(s, c, bs);
         });
@@ -319,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
         }
         rho[i] = r;
         fprime[i] = Fp;
-        xs[i].w = __float_as_uint(Fp);
+        xs[i].w = fprime_word(p, Fp, wi);
         Fi = double(F);
     }
     if (ENERGY) {
@@ -353,7 +419,6 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
     double e = 0.0, w[6] = {0, 0, 0, 0, 0, 0};
     if (i < n) {
         const uint4 pi = xs[i];
-        const float fpi = __uint_as_float(pi.w);
         const int32_t cnt = min(count[i], cap);
         walk_buf<U, 4>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
             float bx = 0.f, by = 0.f, bz = 0.f;
@@ -363,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
                 disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
                 const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
                 // -(dU/dr) / r in the displacement unit: F = g * (dx, dy, dz)
-                const PairOut o = force_term(p, r2, t0 + u * TPA < cnt, fpi + __uint_as_float(pj[u].w));
+                const PairOut o = force_term(p, r2, t0 + u * TPA < cnt, pi.w, pj[u].w);
                 const float g = o.g;
                 bx = __builtin_fmaf(g, dx, bx);
                 by = __builtin_fmaf(g, dy, by);
@@ -591,6 +656,35 @@ int forces_tb(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const i
     p.kp = float(kp);
     p.cp = float(kp * tb->r0 + std::log2(2.0 * tb->A));
     p.lp = float(tb->p / tb->r0);
+    p.A = 1.f;
+    p.gate = gate;
+    return forces_two_pass(box, n, xs, List{cap, idx, cnt}, p, rho, fprime, f, e_atom, ev, flags, ws, w, s);
+}
+
+int forces_tbm(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
+               const md_tbm_t *tb, float *rho, float *fprime, float *f, float *e_atom, double *ev, int32_t flags,
+               void *ws, const WsLayout &w, hipStream_t s, Gate gate)
+{
+    const double two32 = 4294967296.0, log2e = 1.4426950408889634;
+    const double u = disp_unit(box);
+    TBM32 p;
+    p.ax = float(box->L[0] / two32);
+    p.ay = float(box->L[1] / two32);
+    p.az = float(box->L[2] / two32);
+    p.len = float(u);
+    for (int k = 0; k < 3; ++k) {
+        const md_tb_t &t = tb->pair[k];
+        p.cut2u[k] = float(t.rc * t.rc / (u * u));
+        p.rs[k] = float(t.rs);
+        p.iw[k] = float(1.0 / (t.rc - t.rs));
+        const double kq = 2.0 * t.q * log2e / t.r0, kp = t.p * log2e / t.r0;
+        p.kq[k] = float(kq);
+        p.cq[k] = float(kq * t.r0 + std::log2(t.xi * t.xi));
+        p.lq[k] = float(2.0 * t.q / t.r0);
+        p.kp[k] = float(kp);
+        p.cp[k] = float(kp * t.r0 + std::log2(2.0 * t.A));
+        p.lp[k] = float(t.p / t.r0);
+    }
     p.A = 1.f;
     p.gate = gate;
     return forces_two_pass(box, n, xs, List{cap, idx, cnt}, p, rho, fprime, f, e_atom, ev, flags, ws, w, s);

@@ -22,7 +22,7 @@ __device__ __forceinline__ double minimg_d(double d, double L, double hL)
     return d;
 }
 
-template <typename FT>
+template <typename FT, bool KEEP>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(int64_t n, double *__restrict__ x, double *__restrict__ v,
                                                        const FT *__restrict__ f, const double *__restrict__ xref,
                                                        int32_t *__restrict__ status, uint4 *__restrict__ xs,
@@ -46,10 +46,10 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(int64_t n, double *__rest
             const double dz = minimg_d(p[2] - xref[2 * n + i], a.L[2], a.hL[2]);
             moved = ((dx * dx + dy * dy) + dz * dz) > a.half_skin_sq;
         }
-        if (xs)   // whole 16-byte words, nothing read back
+        if (xs)   // whole 16-byte words; with KEEP, bit 0 of the fourth word (the element) carried over
             xs[i] = make_uint4(uint32_t(uint64_t(__double2ll_rn(p[0] * a.k[0]))),
                                uint32_t(uint64_t(__double2ll_rn(p[1] * a.k[1]))),
-                               uint32_t(uint64_t(__double2ll_rn(p[2] * a.k[2]))), 0u);
+                               uint32_t(uint64_t(__double2ll_rn(p[2] * a.k[2]))), KEEP ? xs[i].w & 1u : 0u);
     }
     // one store per wave that saw the condition (idempotent values)
     if (__ballot(moved) && (threadIdx.x % kWave) == 0) status[0] = a.tag;
@@ -86,7 +86,8 @@ __global__ __launch_bounds__(kBlock) void k_kick(int64_t n, double *__restrict__
 // dt/2 * accel for a half step, dt * accel when the closing half kick of the
 // previous step is fused in (same forces).
 int kick_drift(const md_box_t *box, int64_t n, double *x, double *v, const void *f, bool f64, double kick, double dt,
-               const double *xref, double half_skin_sq, int32_t *status, int32_t tag, uint32_t *xs, hipStream_t s)
+               const double *xref, double half_skin_sq, int32_t *status, int32_t tag, uint32_t *xs, hipStream_t s,
+               bool keep_element)
 {
     const uint32_t gb = uint32_t((n + kBlock - 1) / kBlock);
     if (n <= 0) return MD_OK;
@@ -102,11 +103,14 @@ int kick_drift(const md_box_t *box, int64_t n, double *x, double *v, const void 
     a.tag = tag;
     uint4 *q = reinterpret_cast<uint4 *>(xs);
     if (f64)
-        hipLaunchKernelGGL(k_kick_drift<double>, dim3(gb), dim3(kBlock), 0, s, n, x, v, static_cast<const double *>(f),
-                           xref, status, q, a);
+        hipLaunchKernelGGL((k_kick_drift<double, false>), dim3(gb), dim3(kBlock), 0, s, n, x, v,
+                           static_cast<const double *>(f), xref, status, q, a);
+    else if (keep_element)
+        hipLaunchKernelGGL((k_kick_drift<float, true>), dim3(gb), dim3(kBlock), 0, s, n, x, v,
+                           static_cast<const float *>(f), xref, status, q, a);
     else
-        hipLaunchKernelGGL(k_kick_drift<float>, dim3(gb), dim3(kBlock), 0, s, n, x, v, static_cast<const float *>(f),
-                           xref, status, q, a);
+        hipLaunchKernelGGL((k_kick_drift<float, false>), dim3(gb), dim3(kBlock), 0, s, n, x, v,
+                           static_cast<const float *>(f), xref, status, q, a);
     MD_HIP_TRY(hipGetLastError());
     return MD_OK;
 }
@@ -119,7 +123,8 @@ int integrate(int32_t phase, const md_box_t *box, int64_t n, double *x, double *
     const double hk = 0.5 * dt * accel;
     const uint32_t gb = uint32_t((n + kBlock - 1) / kBlock);
     if (phase == MD_KICK_DRIFT)
-        return kick_drift(box, n, x, v, f, f64, hk, dt, xref, half_skin_sq, status, tag, xs, s);
+        return kick_drift(box, n, x, v, f, f64, hk, dt, xref, half_skin_sq, status, tag, xs, s,
+                          (flags & MD_XS_ELEMENT) != 0);
     if (phase != MD_KICK) return MD_ERR_ARG;
     double *part = ws_ptr<double>(ws, w.red1);
     if (int64_t(gb) > w.red_blocks) return MD_ERR_WORKSPACE;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 MD_OK, MD_ERR_ARG, MD_ERR_BOX, MD_ERR_CAPACITY = 0, -1, -2, -3
 MD_ERR_NONFINITE, MD_ERR_HIP, MD_ERR_WORKSPACE = -4, -5, -6
-MD_ENERGY, MD_PAIR_FP64, MD_NO_COMPENSATE, MD_MLP_REUSE = 0x1, 0x2, 0x4, 0x8
+MD_ENERGY, MD_PAIR_FP64, MD_NO_COMPENSATE, MD_MLP_REUSE, MD_XS_ELEMENT = 0x1, 0x2, 0x4, 0x8, 0x10
 MD_KICK_DRIFT, MD_KICK = 1, 2
 MD_SLICE = 8
 MD_MAX_ROW_CAP = 1 << 24
@@ -51,6 +51,18 @@ class TB(C.Structure):
 
 def tb_params(tb: dict) -> TB:
     return TB(*[float(tb[k]) for k in ("A", "xi", "p", "q", "r0", "rs", "rc")])
+
+
+class TBM(C.Structure):
+    """md_tbm_t: tight-binding parameters of the pair kinds 0-0, 0-1, 1-1."""
+    _fields_ = [("pair", TB * 3)]
+
+
+def tbm_params(pairs) -> TBM:
+    m = TBM()
+    for k in range(3):
+        m.pair[k] = tb_params(pairs[k])
+    return m
 
 
 MD_MLP_IN, MD_MLP_HID, MD_MLP_NPARAM = 16, 64, 5313
@@ -89,10 +101,11 @@ class System(C.Structure):
                 ("need_build", C.c_int32), ("phase", C.c_int32), ("timing", C.c_int32), ("pad_", C.c_int32),
                 ("force_ms", C.c_double), ("force_calls", C.c_int64),
                 ("mlp", MLP), ("mlp_w", C.c_void_p), ("dEdG", C.c_void_p), ("idx_in", C.c_void_p),
-                ("cnt_in", C.c_void_p), ("tb", TB)]
+                ("cnt_in", C.c_void_p), ("tb", TB), ("tbm", TBM), ("types", C.c_void_p),
+                ("types_scratch", C.c_void_p)]
 
 
-MD_POT_LJ, MD_POT_EAM, MD_POT_MLP, MD_POT_TB = 0, 1, 2, 3
+MD_POT_LJ, MD_POT_EAM, MD_POT_MLP, MD_POT_TB, MD_POT_TBM = 0, 1, 2, 3, 4
 
 
 class MDError(RuntimeError):
@@ -130,6 +143,9 @@ def lib():
                                     _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
         L.md_forces_tb.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(TB), _vp,
                                    _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_forces_tbm.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(TBM), _vp,
+                                    _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_set_elements.argtypes = [C.c_int64, _vp, _vp, _vp]
         L.md_mlp_descriptors.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(MLP),
                                          _vp, _vp]
         L.md_mlp_eval.argtypes = [C.c_int64, _vp, C.POINTER(MLP), _vp, _vp, _vp, _vp]
@@ -298,6 +314,25 @@ def md_forces_tb(L, n: int, xs, row_cap: int, idx, count, tb: dict, rho, fprime,
                               _ptr(e_atom, torch.float32, n, "e_atom"),
                               _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
                               _stream(stream)), "md_forces_tb")
+
+
+def md_forces_tbm(L, n: int, xs, row_cap: int, idx, count, pairs, rho, fprime, f, ev, flags: int, ws,
+                  stream=None, e_atom=None):
+    import torch
+    p = tbm_params(pairs)
+    _check(lib().md_forces_tbm(C.byref(box(L)), int(n), _ptr(xs, torch.int32, 4 * n, "xs"), int(row_cap),
+                               _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"),
+                               _ptr(count, torch.int32, n, "count"), C.byref(p), _ptr(rho, torch.float32, n, "rho"),
+                               _ptr(fprime, torch.float32, n, "fprime"), _ptr(f, torch.float32, 3 * n, "f"),
+                               _ptr(e_atom, torch.float32, n, "e_atom"),
+                               _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
+                               _stream(stream)), "md_forces_tbm")
+
+
+def md_set_elements(n: int, types, xs, stream=None):
+    import torch
+    _check(lib().md_set_elements(int(n), _ptr(types, torch.int32, n, "types"), _ptr(xs, torch.int32, 4 * n, "xs"),
+                                 _stream(stream)), "md_set_elements")
 
 
 def md_mlp_descriptors(L, n: int, xs, row_cap: int, idx, count, mlp: MLP, G, stream=None):

@@ -24,14 +24,17 @@ class Simulation:
     """One periodic system on one GPU.
 
     potential: "lj" (params eps, sigma, rc), "eam" (Finnis-Sinclair dict),
-    "tb" (second-moment tight-binding dict: A, xi, p, q, r0, rs, rc) or
+    "tb" (second-moment tight-binding dict: A, xi, p, q, r0, rs, rc), "tbm"
+    (two elements: `tbm` = three such dicts for the pair kinds 0-0, 0-1, 1-1,
+    `types` = the element 0/1 of each input atom) or
     "mlp" (descriptor geometry and normalisation `mlp`, an md.MLP, and the
     MD_MLP_NPARAM bfloat16 parameters `mlp_w`, an int16 device tensor).
     Positions and velocities are FP64; forces FP32 (FP64 with pair_fp64).
     Atoms are kept in cell (Morton) order; `ids` maps back to input order.
     """
 
-    def __init__(self, L, x, v, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None, tb=None, mlp=None, mlp_w=None,
+    def __init__(self, L, x, v, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None, tb=None, tbm=None, types=None,
+                 mlp=None, mlp_w=None,
                  skin=0.3, dt=0.005, mass=1.0, force_to_accel=1.0, reach=1, pair_fp64=False,
                  compensate=True, device="cuda", row_cap=None, list_slack=1.2):
         self.L = np.asarray(L, dtype=np.float64).reshape(3)
@@ -41,6 +44,7 @@ class Simulation:
         self.lj = tuple(float(a) for a in lj)
         self.fs = fs
         self.tb = tb
+        self.tbm = tbm
         self.mlp, self.mlp_w = mlp, mlp_w
         if potential == "lj":
             rc = self.lj[2]
@@ -48,6 +52,10 @@ class Simulation:
             rc = max(fs["d"], fs["c"])
         elif potential == "tb":
             rc = float(tb["rc"])
+        elif potential == "tbm":
+            if tbm is None or types is None:
+                raise ValueError("potential 'tbm' needs tbm and types")
+            rc = max(float(t["rc"]) for t in tbm)
         elif potential == "mlp":
             if mlp is None or mlp_w is None:
                 raise ValueError("potential 'mlp' needs mlp and mlp_w")
@@ -76,6 +84,12 @@ class Simulation:
         self.xref = torch.empty_like(self.x)
         self.ids = torch.arange(n, dtype=torch.int32, device=d)
         self._ids2 = torch.empty_like(self.ids)
+        self.types = self._types2 = None
+        if potential == "tbm":
+            self.types = torch.tensor(np.asarray(types, np.int32).reshape(-1), dtype=torch.int32, device=d)
+            if self.types.numel() != n:
+                raise ValueError("types needs one element per atom")
+            self._types2 = torch.empty_like(self.types)
         self.xs = torch.zeros((max(n, 1), 4), dtype=torch.int32, device=d)
         fdt = torch.float64 if pair_fp64 else torch.float32
         self.f = torch.zeros((3, max(n, 1)), dtype=fdt, device=d)
@@ -133,9 +147,14 @@ class Simulation:
             self.x, self._x2 = self._x2, self.x
             self.v, self._v2 = self._v2, self.v
             self.ids, self._ids2 = self._ids2, self.ids
+            if self.types is not None:
+                M.md_permute(n, 1, self.perm, self.types, self._types2, 4)
+                self.types, self._types2 = self._types2, self.types
         self.xref.copy_(self.x)
         if not (self.flags & M.MD_PAIR_FP64):
             M.md_scale_positions(self.L, n, self.x, self.xs)
+            if self.types is not None:
+                M.md_set_elements(n, self.types, self.xs)
         rc, longest = M.md_build_neighbors(self.grid, n, self.x, self.cell_start, self.row_cap, self.idx,
                                            self.count, self.max_count, self.ws)
         if rc == M.MD_ERR_CAPACITY:
@@ -165,6 +184,9 @@ class Simulation:
         elif self.potential == "tb":
             M.md_forces_tb(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.tb, self.rho,
                            self.fprime, self.f, self.ev, fl, self.ws, e_atom=ea)
+        elif self.potential == "tbm":
+            M.md_forces_tbm(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.tbm, self.rho,
+                            self.fprime, self.f, self.ev, fl, self.ws, e_atom=ea)
         else:
             M.md_forces_mlp(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.mlp, self.mlp_w,
                             self.dEdG, self.idx_in, self.cnt_in, ea, self.f, self.ev, fl, self.ws)
@@ -200,7 +222,8 @@ class Simulation:
         m = self._mark("kick_drift")
         M.md_integrate(M.MD_KICK_DRIFT, self.L, self.n, self.x, self.v, self.f, self.dt, self.accel,
                        self.mass, self.xref, self.half_skin_sq, self.status, tag, xs, None,
-                       self.flags & M.MD_PAIR_FP64, self.ws)
+                       (self.flags & M.MD_PAIR_FP64) | (M.MD_XS_ELEMENT if self.types is not None else 0),
+                       self.ws)
         self._done(m)
         self._status_host.copy_(self.status)          # synchronises with the stream
         st = self._status_host.tolist()
@@ -244,8 +267,11 @@ class Simulation:
         S.row_cap = self.row_cap
         if self.tb is not None:
             S.tb = M.tb_params(self.tb)
+        if self.tbm is not None:
+            S.tbm = M.tbm_params(self.tbm)
+            S.types, S.types_scratch = ptr(self.types), ptr(self._types2)
         S.potential = {"lj": M.MD_POT_LJ, "eam": M.MD_POT_EAM, "mlp": M.MD_POT_MLP,
-                       "tb": M.MD_POT_TB}[self.potential]
+                       "tb": M.MD_POT_TB, "tbm": M.MD_POT_TBM}[self.potential]
         if self.potential == "mlp":
             S.mlp, S.mlp_w, S.dEdG = self.mlp, ptr(self.mlp_w), ptr(self.dEdG)
             S.idx_in, S.cnt_in = ptr(self.idx_in), ptr(self.cnt_in)
