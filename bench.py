@@ -374,6 +374,29 @@ def main():
         }
         del sim5, s5
         torch.cuda.empty_cache()
+        # ---- two elements: random alloy and two layers, 4 M atoms ---------
+        for layered in (False, True):
+            name = "tbm_cu_au_layers_100^3" if layered else "tbm_cu75au25_alloy_100^3"
+            log(f"{name}: generating")
+            s6 = inputs.cu_au(layered=layered)
+            sim6 = Simulation(s6.L, s6.x, s6.v, potential="tbm", tbm=inputs.TB2_PAIRS, types=s6.meta["types"],
+                              skin=1.0, dt=1.0, mass=inputs.CU_MASS_AMU,
+                              force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
+            log(f"{name}: running")
+            r6 = run_workload(sim6, 200, 10, torch)
+            f6 = r6["force_ms"]
+            b6 = eam_force_bytes(s6.n, sim6.n_pairs)
+            extra[name] = {
+                "atoms": s6.n, "steps": 200, "value": s6.n * 200 / r6["seconds"], "unit": "atom-steps/s",
+                "ms_per_step": 1e3 * r6["seconds"] / 200, "rebuilds": r6["rebuilds"],
+                "list_entries": sim6.n_pairs, "fraction_element_1": s6.meta["frac_au"],
+                "forces_ms": f6, "forces_GBs": b6 / (f6 * 1e-3) / 1e9,
+                "forces_frac_hbm": b6 / (f6 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "forces_frac_copy": b6 / (f6 * 1e-3) / 1e9 / copy_gbs,
+                "phases_ms_per_call_api": {k: v[0] for k, v in r6["phases"].items()},
+            }
+            del sim6, s6
+            torch.cuda.empty_cache()
         # ---- LJ slab with a dense cluster, about 32 M atoms ----------------
         log("LJ slab + cluster: generating")
         s4 = inputs.lj_slab_cluster()

@@ -223,6 +223,25 @@ def eam_cu(ncell: int = 100, a: float = CU_A0, T: float = 600.0,
                   AMU_A2_FS2_IN_EV, dict(a=a, T=T, seed=seed, ncell=ncell))
 
 
+def cu_au(ncell: int = 100, layered: bool = False, frac_au: float = 0.25, T: float = 600.0,
+          seed: int = 1006) -> System:
+    """Two-element fcc metal on one lattice (a by Vegard's rule for 25 % of
+    element 1): a random alloy with fraction frac_au of element 1 (the
+    paper's Alloy system), or two layers, element 0 below z = L/2 and
+    element 1 above (its Layer system).  meta["types"] holds the element of
+    each atom.  One mass (Cu's) for both elements."""
+    a = (1.0 - 0.25) * CU_A0 + 0.25 * AU_A0
+    x = fcc_sites(ncell, ncell, ncell, a)
+    L = np.full(3, ncell * a)
+    if layered:
+        t = (x[:, 2] >= 0.5 * L[2]).astype(np.int32)
+    else:
+        t = (rng_for(seed, "elements").random(len(x)) < frac_au).astype(np.int32)
+    v = maxwell_boltzmann(len(x), T, CU_MASS_AMU, KB_EV, AMU_A2_FS2_IN_EV, rng_for(seed, "velocity"))
+    return System("cu_au_layers" if layered else "cu_au_alloy", L, x, v, CU_MASS_AMU, KB_EV, AMU_A2_FS2_IN_EV,
+                  dict(a=a, T=T, seed=seed, ncell=ncell, types=t, frac_au=float(t.mean())))
+
+
 def jitter(sys: System, sigma: float, seed: int) -> System:
     """Copy of `sys` with Gaussian position noise of width sigma (a stand-in
     for a thermalised snapshot in per-call parity tests)."""
