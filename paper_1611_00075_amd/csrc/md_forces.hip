@@ -215,13 +215,17 @@ struct TB32 {
 // Two elements: the tight-binding constants per pair kind k = t_i + t_j
 // (0: 0-0, 1: 0-1, 2: 1-1).  The element of atom i is bit 0 of the fourth
 // word of its scaled coordinates (on entry the element itself; after pass 1
-// F'_i with its lowest mantissa bit replaced by the element).
+// F'_i with its lowest mantissa bit replaced by the element).  With
+// COMMON_CUT all kinds share the smooth cutoff (kind 0's values are used),
+// which leaves four constants to choose per pair; the base-e slopes follow
+// from the base-2 ones (l = k ln 2).
+template <bool COMMON_CUT>
 struct TBM32 {
     float ax, ay, az;       // L_a / 2^32 (non-cubic boxes)
     float len;              // length unit of the displacements (s or 1)
     float cut2u[3], rs[3], iw[3];
-    float kq[3], cq[3], lq[3];
-    float kp[3], cp[3], lp[3];
+    float kq[3], cq[3];
+    float kp[3], cp[3];
     float A;                // embedding prefactor (1)
     Gate gate;
     static constexpr int kRhoWords = 4;
@@ -314,26 +318,37 @@ __device__ __forceinline__ float sel3(const float (&v)[3], uint32_t k)
     return k == 0u ? v[0] : (k == 1u ? v[1] : v[2]);
 }
 
-__device__ __forceinline__ float rho_term(const TBM32 &p, float r2, bool valid, uint32_t wi, uint32_t wj)
+template <bool CC>
+__device__ __forceinline__ float cut_sel(const float (&v)[3], uint32_t k)
 {
-    const uint32_t k = (wi & 1u) + (wj & 1u);
-    const float psi = tb_psi(__builtin_amdgcn_sqrtf(r2) * p.len, sel3(p.rs, k), sel3(p.iw, k), sel3(p.kq, k),
-                             sel3(p.cq, k));
-    return (valid && r2 < sel3(p.cut2u, k)) ? psi : 0.f;
+    return CC ? v[0] : sel3(v, k);
 }
 
-__device__ __forceinline__ PairOut force_term(const TBM32 &p, float r2, bool valid, uint32_t wi, uint32_t wj)
+template <bool CC>
+__device__ __forceinline__ float rho_term(const TBM32<CC> &p, float r2, bool valid, uint32_t wi, uint32_t wj)
 {
     const uint32_t k = (wi & 1u) + (wj & 1u);
-    const bool in = valid && r2 < sel3(p.cut2u, k);
+    const float psi = tb_psi(__builtin_amdgcn_sqrtf(r2) * p.len, cut_sel<CC>(p.rs, k), cut_sel<CC>(p.iw, k),
+                             sel3(p.kq, k), sel3(p.cq, k));
+    return (valid && r2 < cut_sel<CC>(p.cut2u, k)) ? psi : 0.f;
+}
+
+template <bool CC>
+__device__ __forceinline__ PairOut force_term(const TBM32<CC> &p, float r2, bool valid, uint32_t wi, uint32_t wj)
+{
+    constexpr float kLn2 = 0.693147180559945309f;
+    const uint32_t k = (wi & 1u) + (wj & 1u);
+    const bool in = valid && r2 < cut_sel<CC>(p.cut2u, k);
     const float ru = __builtin_amdgcn_sqrtf(r2);
     const float fsum = __uint_as_float(wi & ~1u) + __uint_as_float(wj & ~1u);
-    const float2 o = tb_force(ru * p.len, ru, fsum, sel3(p.rs, k), sel3(p.iw, k), sel3(p.kq, k), sel3(p.cq, k),
-                              sel3(p.lq, k), sel3(p.kp, k), sel3(p.cp, k), sel3(p.lp, k));
+    const float kq = sel3(p.kq, k), kp = sel3(p.kp, k);
+    const float2 o = tb_force(ru * p.len, ru, fsum, cut_sel<CC>(p.rs, k), cut_sel<CC>(p.iw, k), kq, sel3(p.cq, k),
+                              kq * kLn2, kp, sel3(p.cp, k), kp * kLn2);
     return {in ? o.x : 0.f, in ? o.y : 0.f, in};
 }
 
-__device__ __forceinline__ uint32_t fprime_word(const TBM32 &, float fp, uint32_t wi)
+template <bool CC>
+__device__ __forceinline__ uint32_t fprime_word(const TBM32<CC> &, float fp, uint32_t wi)
 {
     return (__float_as_uint(fp) & ~1u) | (wi & 1u);
 }
@@ -661,13 +676,12 @@ int forces_tb(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const i
     return forces_two_pass(box, n, xs, List{cap, idx, cnt}, p, rho, fprime, f, e_atom, ev, flags, ws, w, s);
 }
 
-int forces_tbm(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
-               const md_tbm_t *tb, float *rho, float *fprime, float *f, float *e_atom, double *ev, int32_t flags,
-               void *ws, const WsLayout &w, hipStream_t s, Gate gate)
+template <bool CC>
+static TBM32<CC> tbm_constants(const md_box_t *box, const md_tbm_t *tb, Gate gate)
 {
     const double two32 = 4294967296.0, log2e = 1.4426950408889634;
     const double u = disp_unit(box);
-    TBM32 p;
+    TBM32<CC> p;
     p.ax = float(box->L[0] / two32);
     p.ay = float(box->L[1] / two32);
     p.az = float(box->L[2] / two32);
@@ -680,14 +694,26 @@ int forces_tbm(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const 
         const double kq = 2.0 * t.q * log2e / t.r0, kp = t.p * log2e / t.r0;
         p.kq[k] = float(kq);
         p.cq[k] = float(kq * t.r0 + std::log2(t.xi * t.xi));
-        p.lq[k] = float(2.0 * t.q / t.r0);
         p.kp[k] = float(kp);
         p.cp[k] = float(kp * t.r0 + std::log2(2.0 * t.A));
-        p.lp[k] = float(t.p / t.r0);
     }
     p.A = 1.f;
     p.gate = gate;
-    return forces_two_pass(box, n, xs, List{cap, idx, cnt}, p, rho, fprime, f, e_atom, ev, flags, ws, w, s);
+    return p;
+}
+
+int forces_tbm(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
+               const md_tbm_t *tb, float *rho, float *fprime, float *f, float *e_atom, double *ev, int32_t flags,
+               void *ws, const WsLayout &w, hipStream_t s, Gate gate)
+{
+    const md_tb_t *q = tb->pair;
+    const bool common = q[0].rs == q[1].rs && q[0].rs == q[2].rs && q[0].rc == q[1].rc && q[0].rc == q[2].rc;
+    const List l{cap, idx, cnt};
+    if (common)
+        return forces_two_pass(box, n, xs, l, tbm_constants<true>(box, tb, gate), rho, fprime, f, e_atom, ev, flags,
+                               ws, w, s);
+    return forces_two_pass(box, n, xs, l, tbm_constants<false>(box, tb, gate), rho, fprime, f, e_atom, ev, flags, ws,
+                           w, s);
 }
 
 }  // namespace md

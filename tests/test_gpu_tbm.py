@@ -36,7 +36,12 @@ def _system(orc, ncell, jit, seed, layered):
     return x, L, t
 
 
-def _gpu_tbm(M, x, L, t):
+# per-kind smooth cutoffs (a separate device path from the shared cutoff)
+PAIRS_CUTS = (dict(inputs.TB2_CU, rs=4.6, rc=5.1), dict(inputs.TB2_CUAU, rs=5.0, rc=5.5),
+              dict(inputs.TB2_AU, rs=5.2, rc=5.7))
+
+
+def _gpu_tbm(M, x, L, t, pairs=PAIRS):
     from test_gpu_parity import _gpu_lists
     n = len(x)
     rows, st = _gpu_lists(M, x, L, R_LIST)
@@ -49,7 +54,7 @@ def _gpu_tbm(M, x, L, t):
     fp = torch.zeros(n, dtype=torch.float32, device="cuda")
     ev = torch.zeros(8, dtype=torch.float64, device="cuda")
     ea = torch.zeros(n, dtype=torch.float32, device="cuda")
-    M.md_forces_tbm(L, n, xsc, st["cap"], st["idx"], st["cnt"], PAIRS, rho, fp, f, ev, M.MD_ENERGY, st["ws"],
+    M.md_forces_tbm(L, n, xsc, st["cap"], st["idx"], st["cnt"], pairs, rho, fp, f, ev, M.MD_ENERGY, st["ws"],
                     e_atom=ea)
     out = dict(ev=ev.cpu().numpy(), w=xsc[:, 3].cpu().numpy().astype(np.uint32))
     for k, v in (("rho", rho), ("fprime", fp), ("e_atom", ea)):
@@ -63,12 +68,13 @@ def _gpu_tbm(M, x, L, t):
     return out
 
 
-@pytest.mark.parametrize("layered,seed", [(False, 61), (True, 62)])
-def test_forces_tbm_vs_oracle(M, orc, layered, seed):
+@pytest.mark.parametrize("layered,seed,pairs", [(False, 61, PAIRS), (True, 62, PAIRS), (False, 64, PAIRS_CUTS)],
+                         ids=["alloy", "layers", "alloy-own-cutoffs"])
+def test_forces_tbm_vs_oracle(M, orc, layered, seed, pairs):
     x, L, t = _system(orc, 6, 0.1, seed, layered)
-    g = _gpu_tbm(M, x, L, t)
+    g = _gpu_tbm(M, x, L, t, pairs)
     oc, ic = orc.neighbors_cells(x, L, R_LIST)
-    r = orc.forces_tbm(x, L, oc, ic, t, PAIRS)
+    r = orc.forces_tbm(x, L, oc, ic, t, pairs)
     assert np.abs(g["rho"] - r["rho"]).max() / r["rho"].max() < 1e-5
     assert np.abs(g["e_atom"] - r["e_atom"]).max() < 2e-6 * np.abs(r["e_atom"]).max()
     err = np.linalg.norm(g["f"] - r["f"]) / np.linalg.norm(r["f"])
