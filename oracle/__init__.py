@@ -81,6 +81,9 @@ def _declare(L):
                                C.POINTER(TBParams), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_forces_tbm.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i32p, _i64p, _i32p,
                                 C.POINTER(TBParams), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_forces_tab.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
+                                C.POINTER(TabParams), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_tab_eval.argtypes = [C.c_int32, C.c_double, _dp, _dp, C.c_double, _dp, _dp]
     L.or_md_run.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                             C.POINTER(MDParams), C.c_int64, _dp, _dp, _dp]
     L.or_md_run.restype = C.c_int64
@@ -209,6 +212,51 @@ def forces_tbm(x, L, off, idx, types, pairs):
                         _p(np.ascontiguousarray(off, np.int64), _i64p),
                         _p(np.ascontiguousarray(idx, np.int32), _i32p), prm,
                         _p(rho), _p(fp), *[_p(c) for c in f], _p(ea), _p(ev))
+    return dict(rho=rho, fprime=fp, f=np.stack(f, axis=1), e_atom=ea, ev=ev)
+
+
+class TabParams(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nrho", C.c_int32), ("dr", C.c_double), ("drho", C.c_double),
+                ("psi", _dp), ("dpsi", _dp), ("phi", _dp), ("dphi", _dp), ("F", _dp), ("dF", _dp)]
+
+
+def _tab_struct(tab):
+    arrs = {k: np.ascontiguousarray(tab[k], dtype=np.float64) for k in ("psi", "dpsi", "phi", "dphi", "F", "dF")}
+    nr, nrho = len(arrs["psi"]), len(arrs["F"])
+    assert all(len(arrs[k]) == nr for k in ("dpsi", "phi", "dphi")) and len(arrs["dF"]) == nrho
+    prm = TabParams(nr, nrho, float(tab["dr"]), float(tab["drho"]), *[_p(arrs[k]) for k in
+                                                                       ("psi", "dpsi", "phi", "dphi", "F", "dF")])
+    return prm, arrs
+
+
+def tab_eval(f, df, h, u):
+    """One tabulated function (values f, slopes df at knots k h) at the
+    points u: (values, slopes) of its cubic Hermite interpolant."""
+    f = np.ascontiguousarray(f, np.float64)
+    df = np.ascontiguousarray(df, np.float64)
+    u = np.atleast_1d(np.asarray(u, np.float64))
+    val, slope = np.zeros(len(u)), np.zeros(len(u))
+    v, s = C.c_double(), C.c_double()
+    for k, uk in enumerate(u):
+        lib().or_tab_eval(len(f), float(h), _p(f), _p(df), float(uk), C.byref(v), C.byref(s))
+        val[k], slope[k] = v.value, s.value
+    return val, slope
+
+
+def forces_tab(x, L, off, idx, tab):
+    """FP64 tabulated embedded-atom potential.  `tab`: dict with dr, drho and
+    the knot arrays psi, dpsi, phi, dphi (r_k = k dr) and F, dF
+    (rho_k = k drho).  Output as forces_eam."""
+    xs = _soa(x)
+    n = len(xs[0])
+    f = [np.zeros(n) for _ in range(3)]
+    rho, fp, ea, ev = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(8)
+    prm, keep = _tab_struct(tab)
+    lib().or_forces_tab(n, _p(_box(L)), *[_p(c) for c in xs],
+                        _p(np.ascontiguousarray(off, np.int64), _i64p),
+                        _p(np.ascontiguousarray(idx, np.int32), _i32p), C.byref(prm),
+                        _p(rho), _p(fp), *[_p(c) for c in f], _p(ea), _p(ev))
+    del keep
     return dict(rho=rho, fprime=fp, f=np.stack(f, axis=1), e_atom=ea, ev=ev)
 
 

@@ -397,6 +397,105 @@ void or_forces_tb(int64_t n, const double L[3], const double *x,
     for (int a = 0; a < 6; ++a) ev[2 + a] = W[a];
 }
 
+/* ------------------------------------------------------------------ */
+/* tabulated functions: cubic Hermite interpolation between knots       */
+/* ------------------------------------------------------------------ */
+
+/* The interpolant on [u_k, u_k + h] with s = (u - u_k)/h:
+ *   f = H00(s) f_k + H10(s) h f'_k + H01(s) f_{k+1} + H11(s) h f'_{k+1},
+ * H00 = 2s^3 - 3s^2 + 1, H10 = s^3 - 2s^2 + s, H01 = -2s^3 + 3s^2,
+ * H11 = s^3 - s^2 (the textbook cubic Hermite basis); its slope is the
+ * derivative of the same expression in u.  Outside [u_0, u_{m-1}] the
+ * tangent line at the end knot. */
+void or_tab_eval(int32_t m, double h, const double *f, const double *df,
+                 double u, double *val, double *slope)
+{
+    const double umax = (m - 1) * h;
+    if (u < 0.0) {
+        *val = f[0] + df[0] * u;
+        *slope = df[0];
+        return;
+    }
+    if (u > umax) {
+        *val = f[m - 1] + df[m - 1] * (u - umax);
+        *slope = df[m - 1];
+        return;
+    }
+    int32_t k = (int32_t)floor(u / h);
+    if (k > m - 2) k = m - 2;
+    const double s = (u - k * h) / h;
+    const double s2 = s * s, s3 = s2 * s;
+    const double H00 = 2.0 * s3 - 3.0 * s2 + 1.0, H10 = s3 - 2.0 * s2 + s;
+    const double H01 = -2.0 * s3 + 3.0 * s2, H11 = s3 - s2;
+    const double dH00 = 6.0 * s2 - 6.0 * s, dH10 = 3.0 * s2 - 4.0 * s + 1.0;
+    const double dH01 = -6.0 * s2 + 6.0 * s, dH11 = 3.0 * s2 - 2.0 * s;
+    *val = H00 * f[k] + H10 * h * df[k] + H01 * f[k + 1] + H11 * h * df[k + 1];
+    *slope = (dH00 * f[k] + dH01 * f[k + 1]) / h + dH10 * df[k] + dH11 * df[k + 1];
+}
+
+void or_forces_tab(int64_t n, const double L[3], const double *x,
+                   const double *y, const double *z, const int64_t *offsets,
+                   const int32_t *idx, const or_tab_t *p, double *rho,
+                   double *fprime, double *fx, double *fy, double *fz,
+                   double *e_atom, double ev[8])
+{
+    const double rc = (p->nr - 1) * p->dr, rc2 = rc * rc;
+    double d[3];
+    /* step 1: rho_i = sum_{j != i} psi(r_ij) */
+    for (int64_t i = 0; i < n; ++i) rho[i] = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            int64_t j = idx[k];
+            if (j <= i) continue;
+            double r2 = dist2(L, x, y, z, i, j, d);
+            if (!(r2 < rc2)) continue;
+            double r = sqrt(r2), psi, dpsi;
+            if (!(r < rc)) continue;
+            or_tab_eval(p->nr, p->dr, p->psi, p->dpsi, r, &psi, &dpsi);
+            rho[i] += psi;
+            rho[j] += psi;
+        }
+    /* step 2: embedding F(rho_i) and F'(rho_i) */
+    double Eemb = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double F, Fp;
+        or_tab_eval(p->nrho, p->drho, p->F, p->dF, rho[i], &F, &Fp);
+        fprime[i] = Fp;
+        Eemb += F;
+        if (e_atom) e_atom[i] = F;
+        fx[i] = fy[i] = fz[i] = 0.0;
+    }
+    /* step 3: pair interaction and forces */
+    double Epair = 0.0, W[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            int64_t j = idx[k];
+            if (j <= i) continue;
+            double r2 = dist2(L, x, y, z, i, j, d);
+            if (!(r2 < rc2)) continue;
+            double r = sqrt(r2), psi, dpsi, Phi, dPhi;
+            if (!(r < rc)) continue;
+            or_tab_eval(p->nr, p->dr, p->psi, p->dpsi, r, &psi, &dpsi);
+            or_tab_eval(p->nr, p->dr, p->phi, p->dphi, r, &Phi, &dPhi);
+            double dUdr = (fprime[i] + fprime[j]) * dpsi + dPhi;
+            Epair += Phi;
+            if (e_atom) {
+                e_atom[i] += 0.5 * Phi;
+                e_atom[j] += 0.5 * Phi;
+            }
+            double R[3] = {-d[0], -d[1], -d[2]};
+            double g = -dUdr / r; /* F_i = g R */
+            fx[i] += g * R[0]; fy[i] += g * R[1]; fz[i] += g * R[2];
+            fx[j] -= g * R[0]; fy[j] -= g * R[1]; fz[j] -= g * R[2];
+            W[0] += g * R[0] * R[0]; W[1] += g * R[1] * R[1];
+            W[2] += g * R[2] * R[2]; W[3] += g * R[0] * R[1];
+            W[4] += g * R[0] * R[2]; W[5] += g * R[1] * R[2];
+        }
+    ev[0] = Eemb + Epair;
+    ev[1] = Eemb;
+    for (int a = 0; a < 6; ++a) ev[2 + a] = W[a];
+}
+
 void or_forces_tbm(int64_t n, const double L[3], const double *x,
                    const double *y, const double *z, const int32_t *types,
                    const int64_t *offsets, const int32_t *idx,

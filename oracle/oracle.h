@@ -133,6 +133,34 @@ void or_forces_tbm(int64_t n, const double L[3], const double *x,
                    double *fx, double *fy, double *fz, double *e_atom,
                    double ev[8]);
 
+/* Tabulated functions (Sec. 3.1 names piecewise-defined psi and Phi for its
+ * iron potential; Sec. 5 equates an interpolation table with such a
+ * piecewise definition).  One element, the form of Eqs. (1)-(2):
+ *   psi, Phi given at r_k = k dr (k = 0 .. nr-1) by value and slope;
+ *   F given at rho_k = k drho (k = 0 .. nrho-1) by value and slope.
+ * Between two knots a function is the cubic Hermite interpolant of the
+ * values and slopes at the two knots.  psi = Phi = 0 for r >= rc =
+ * (nr-1) dr (strict: a pair counts when r < rc).  Below rho_0 = 0 and above
+ * rho_{nrho-1}, F continues along its tangent at that end knot.
+ * Same three steps and outputs as or_forces_eam;
+ * e_atom = F(rho_i) + 1/2 sum_j Phi(r_ij). */
+typedef struct {
+    int32_t nr, nrho;
+    double dr, drho;
+    const double *psi, *dpsi, *phi, *dphi, *F, *dF;
+} or_tab_t;
+
+void or_forces_tab(int64_t n, const double L[3], const double *x,
+                   const double *y, const double *z, const int64_t *offsets,
+                   const int32_t *idx, const or_tab_t *p, double *rho,
+                   double *fprime, double *fx, double *fy, double *fz,
+                   double *e_atom, double ev[8]);
+
+/* One tabulated function (values f[m], slopes df[m] at u_k = k h) at u:
+ * *val and *slope of its interpolant (the F rule outside [0, (m-1) h]). */
+void or_tab_eval(int32_t m, double h, const double *f, const double *df,
+                 double u, double *val, double *slope);
+
 /* ---- velocity-Verlet molecular dynamics (Sec. 3.3) ---- */
 
 enum { OR_POT_LJ = 0, OR_POT_EAM = 1 };

@@ -242,6 +242,33 @@ def cu_au(ncell: int = 100, layered: bool = False, frac_au: float = 0.25, T: flo
                   dict(a=a, T=T, seed=seed, ncell=ncell, types=t, frac_au=float(t.mean())))
 
 
+def fs_table(fs: dict = FS_CU, dr: float = 0.005, drho: float = 0.05, rho_max: float = 100.0) -> dict:
+    """Input tables of the tabulated embedded-atom form sampled from a
+    Finnis-Sinclair parameter set (its functions psi = (r - d)^2 below d,
+    V = (r - c)^2 (c0 + c1 r + c2 r^2) below c, F = -A sqrt(rho)): values and
+    slopes at r_k = k dr up to d (dr must divide d and c) and at
+    rho_k = k drho up to rho_max.  At rho = 0, where F has no finite slope,
+    the slope given is that of the chord to the next knot."""
+    d, c = fs["d"], fs["c"]
+    nr = int(round(d / dr)) + 1
+    if abs((nr - 1) * dr - d) > 1e-9 or abs(round(c / dr) * dr - c) > 1e-9:
+        raise ValueError("dr must divide both cutoffs")
+    r = np.arange(nr) * dr
+    psi = np.where(r < d, (r - d) ** 2, 0.0)
+    dpsi = np.where(r < d, 2.0 * (r - d), 0.0)
+    q = fs["c0"] + fs["c1"] * r + fs["c2"] * r * r
+    dq = fs["c1"] + 2.0 * fs["c2"] * r
+    phi = np.where(r < c, (r - c) ** 2 * q, 0.0)
+    dphi = np.where(r < c, 2.0 * (r - c) * q + (r - c) ** 2 * dq, 0.0)
+    nrho = int(round(rho_max / drho)) + 1
+    rho = np.arange(nrho) * drho
+    F = -fs["A"] * np.sqrt(rho)
+    dF = np.empty(nrho)
+    dF[1:] = -0.5 * fs["A"] / np.sqrt(rho[1:])
+    dF[0] = (F[1] - F[0]) / drho
+    return dict(dr=dr, drho=drho, psi=psi, dpsi=dpsi, phi=phi, dphi=dphi, F=F, dF=dF)
+
+
 def jitter(sys: System, sigma: float, seed: int) -> System:
     """Copy of `sys` with Gaussian position noise of width sigma (a stand-in
     for a thermalised snapshot in per-call parity tests)."""
