@@ -256,6 +256,53 @@ int md_forces_tbm(const md_box_t *box, int64_t n, uint32_t *xs,
 int md_set_elements(int64_t n, const int32_t *types, uint32_t *xs,
                     void *stream);
 
+/* ---- tabulated embedded-atom functions ----
+ *
+ * Sec. 3.1 names piecewise-defined psi and Phi for its iron potential, and
+ * Sec. 5 takes an interpolation table to be such a piecewise definition.
+ * One element, the form of Eqs. (1)-(2) with psi, Phi and F given as
+ * tables:
+ *   psi, Phi at r_k = k dr (k = 0 .. nr-1) by value and slope,
+ *   F at rho_k = k drho (k = 0 .. nrho-1) by value and slope;
+ * between two knots a function is the cubic Hermite interpolant of the
+ * values and slopes at the two knots; psi = Phi = 0 for r >= rc =
+ * (nr-1) dr; below rho = 0 and above rho_{nrho-1}, F continues along the
+ * tangent at that end knot. */
+#define MD_TAB_MAX_KNOTS 2001   /* knots of psi and Phi (rc / dr <= 2000) */
+#define MD_TAB_MAX_RHO_KNOTS (1 << 24)
+
+typedef struct md_tab {
+    int32_t nr;      /* knots of psi and Phi, 2 .. MD_TAB_MAX_KNOTS */
+    int32_t nrho;    /* knots of F, 2 .. MD_TAB_MAX_RHO_KNOTS */
+    double dr;       /* knot spacing in r (> 0) */
+    double drho;     /* knot spacing in rho (> 0) */
+} md_tab_t;
+
+/* Bytes of the device table of `tab`: 32 (nr-1) + 16 (nrho-1); 0 for an
+ * invalid tab. */
+int64_t md_tab_bytes(const md_tab_t *tab);
+
+/* Fills the device table (caller-owned, md_tab_bytes bytes, 16-byte
+ * aligned) from host FP64 arrays: psi, dpsi, phi, dphi [nr] (values and
+ * slopes at r_k), F, dF [nrho] (at rho_k).  The table holds per interval
+ * the FP32 coefficients of the interpolant in powers of the position in
+ * the interval (psi intervals, then Phi intervals, then F intervals).  The
+ * copy is enqueued on `stream` and waited for before returning.
+ * MD_ERR_ARG for a bad tab, a null pointer or a non-finite value. */
+int md_tab_pack(const md_tab_t *tab, const double *psi, const double *dpsi,
+                const double *phi, const double *dphi, const double *F,
+                const double *dF, void *table, void *stream);
+
+/* The three steps of Sec. 3.1 with tabulated psi, Phi and F (table from
+ * md_tab_pack for the same tab).  Same outputs as md_forces_eam, with Phi
+ * in place of V (e_atom[i] = F(rho_i) + 1/2 sum_j Phi(r_ij)).  The list
+ * must reach rc = (nr-1) dr. */
+int md_forces_tab(const md_box_t *box, int64_t n, uint32_t *xs,
+                  int32_t row_cap, const int32_t *idx, const int32_t *count,
+                  const md_tab_t *tab, const void *table, float *rho,
+                  float *fprime, float *f, float *e_atom, double *ev,
+                  int32_t flags, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- steps a8/a9: learned descriptor-MLP potential ----
  *
  * A learned stand-in for the embedded-atom energy of Eqs. (1)-(2): like
@@ -404,6 +451,7 @@ int md_integrate(int32_t phase, const md_box_t *box, int64_t n, double *x,
 #define MD_POT_MLP 2
 #define MD_POT_TB  3
 #define MD_POT_TBM 4
+#define MD_POT_TAB 5
 
 /* One system for md_run.  The caller fills every field (device buffers are
  * caller-owned; sizes as for the calls above) and keeps the struct between
@@ -433,7 +481,7 @@ typedef struct md_system {
     size_t ws_bytes;
     int32_t row_cap;
     int32_t row_cap_needed;     /* out: set with MD_ERR_CAPACITY */
-    int32_t potential;          /* MD_POT_LJ, MD_POT_EAM, MD_POT_MLP, MD_POT_TB or MD_POT_TBM */
+    int32_t potential;          /* MD_POT_LJ, MD_POT_EAM, MD_POT_MLP, MD_POT_TB, MD_POT_TBM or MD_POT_TAB */
     int32_t flags;              /* MD_PAIR_FP64 (LJ only), MD_NO_COMPENSATE */
     int32_t need_build;         /* 1: build lists (and forces) before stepping */
     int32_t phase;              /* 0: at a step boundary; 1: a step is in flight */
@@ -448,13 +496,15 @@ typedef struct md_system {
     md_tb_t tb;                 /* MD_POT_TB (rho, fprime as for MD_POT_EAM) */
     md_tbm_t tbm;               /* MD_POT_TBM (rho, fprime as for MD_POT_EAM) */
     int32_t *types, *types_scratch;   /* MD_POT_TBM: [n] element of each sorted atom, permuted at builds */
+    md_tab_t tab;               /* MD_POT_TAB (rho, fprime as for MD_POT_EAM) */
+    const void *tab_table;      /* MD_POT_TAB: device table from md_tab_pack */
 } md_system_t;
 
 /* Runs `steps` velocity-Verlet steps (Sec. 3.3) of the path: kick + drift
  * with the rebuild check, md_bin_cells + md_permute + md_scale_positions +
  * md_build_neighbors whenever some atom moved more than skin/2 since the
  * last build, forces (md_forces_lj, md_forces_eam, md_forces_mlp,
- * md_forces_tb or md_forces_tbm), kick.  Between two
+ * md_forces_tb, md_forces_tbm or md_forces_tab), kick.  Between two
  * steps the closing half kick and the next opening half kick are applied as
  * one kick with the same forces.  On entry with need_build set (a new
  * system) the lists and forces are built first; otherwise f must hold the

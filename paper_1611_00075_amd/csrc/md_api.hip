@@ -301,6 +301,34 @@ int md_set_elements(int64_t n, const int32_t *types, uint32_t *xs, void *stream)
     return set_elements(n, types, xs, as_stream(stream));
 }
 
+int64_t md_tab_bytes(const md_tab_t *tab) { return tab_bytes(tab); }
+
+int md_tab_pack(const md_tab_t *tab, const double *psi, const double *dpsi, const double *phi, const double *dphi,
+                const double *F, const double *dF, void *table, void *stream)
+{
+    if (!tab_ok(tab) || !psi || !dpsi || !phi || !dphi || !F || !dF || !table) return MD_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(table) % 16) return MD_ERR_ARG;
+    return tab_pack(tab, psi, dpsi, phi, dphi, F, dF, table, as_stream(stream));
+}
+
+int md_forces_tab(const md_box_t *box, int64_t n, uint32_t *xs, int32_t row_cap, const int32_t *idx,
+                  const int32_t *count, const md_tab_t *tab, const void *table, float *rho, float *fprime, float *f,
+                  float *e_atom, double *ev, int32_t flags, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!box_ok(box)) return MD_ERR_BOX;
+    if (!tab_ok(tab)) return MD_ERR_ARG;
+    if (n < 0 || n > kMaxAtomsXs || row_cap < 1 || row_cap % 8 || row_cap > MD_MAX_ROW_CAP) return MD_ERR_ARG;
+    if (flags & ~(MD_ENERGY | MD_NO_COMPENSATE)) return MD_ERR_ARG;
+    if (n > 0 && (!xs || !idx || !count || !rho || !fprime || !f || !table)) return MD_ERR_ARG;
+    if (table && reinterpret_cast<uintptr_t>(table) % 16) return MD_ERR_ARG;
+    if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
+    if (e_atom && !(flags & MD_ENERGY)) return MD_ERR_ARG;
+    WsLayout w;
+    if (int rc = ws_check_n(n, ws, ws_bytes, w)) return rc;
+    return forces_tab(box, n, xs, row_cap, idx, count, tab, table, rho, fprime, f, e_atom, ev, flags, ws, w,
+                      as_stream(stream));
+}
+
 int md_mlp_descriptors(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t row_cap, const int32_t *idx,
                        const int32_t *count, const md_mlp_t *mlp, float *G, void *stream)
 {
@@ -397,7 +425,10 @@ int md_run(md_system_t *sys, int64_t steps, void *stream)
     if (!sys || steps < 0 || !box_ok(&sys->box) || !grid_ok(&sys->grid) || sys->n < 0 || sys->n > kMaxAtoms)
         return MD_ERR_ARG;
     if (sys->potential != MD_POT_LJ && sys->potential != MD_POT_EAM && sys->potential != MD_POT_MLP &&
-        sys->potential != MD_POT_TB && sys->potential != MD_POT_TBM)
+        sys->potential != MD_POT_TB && sys->potential != MD_POT_TBM && sys->potential != MD_POT_TAB)
+        return MD_ERR_ARG;
+    if (sys->potential == MD_POT_TAB &&
+        (!tab_ok(&sys->tab) || !sys->tab_table || reinterpret_cast<uintptr_t>(sys->tab_table) % 16))
         return MD_ERR_ARG;
     if (sys->potential == MD_POT_TB && !tb_ok(&sys->tb)) return MD_ERR_ARG;
     if (sys->potential == MD_POT_TBM &&
@@ -418,7 +449,8 @@ int md_run(md_system_t *sys, int64_t steps, void *stream)
             !sys->status)
             return MD_ERR_ARG;
         if (!f64 && !sys->xs) return MD_ERR_ARG;
-        if ((sys->potential == MD_POT_EAM || sys->potential == MD_POT_TB || sys->potential == MD_POT_TBM) &&
+        if ((sys->potential == MD_POT_EAM || sys->potential == MD_POT_TB || sys->potential == MD_POT_TBM ||
+             sys->potential == MD_POT_TAB) &&
             (!sys->rho || !sys->fprime))
             return MD_ERR_ARG;
         if (sys->potential == MD_POT_TBM && (!sys->types || !sys->types_scratch)) return MD_ERR_ARG;

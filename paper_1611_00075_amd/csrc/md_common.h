@@ -159,6 +159,13 @@ int forces_tbm(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, 
                float *, float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t,
                Gate = {});
 int set_elements(int64_t, const int32_t *, uint32_t *, hipStream_t);
+bool tab_ok(const md_tab_t *);
+int64_t tab_bytes(const md_tab_t *);
+int tab_pack(const md_tab_t *, const double *, const double *, const double *, const double *, const double *,
+             const double *, void *, hipStream_t);
+int forces_tab(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, const int32_t *, const md_tab_t *,
+               const void *, float *, float *, float *, float *, double *, int32_t, void *, const WsLayout &,
+               hipStream_t, Gate = {});
 int integrate(int32_t, const md_box_t *, int64_t, double *, double *, const void *, double, double, double,
               const double *, double, int32_t *, int32_t, uint32_t *, double *, int32_t, void *, const WsLayout &,
               hipStream_t);

@@ -154,6 +154,10 @@ int forces(md_system_t *sys, const WsLayout &w, hipStream_t s, Gate gate = {})
         return forces_tbm(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->tbm, sys->rho,
                           sys->fprime, static_cast<float *>(sys->f), nullptr, nullptr, sys->flags & MD_NO_COMPENSATE,
                           sys->ws, w, s, gate);
+    if (sys->potential == MD_POT_TAB)
+        return forces_tab(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->tab, sys->tab_table,
+                          sys->rho, sys->fprime, static_cast<float *>(sys->f), nullptr, nullptr,
+                          sys->flags & MD_NO_COMPENSATE, sys->ws, w, s, gate);
     if (sys->potential == MD_POT_TB)
         return forces_tb(&sys->box, sys->n, sys->xs, sys->row_cap, sys->idx, sys->count, &sys->tb, sys->rho,
                          sys->fprime, static_cast<float *>(sys->f), nullptr, nullptr, sys->flags & MD_NO_COMPENSATE,

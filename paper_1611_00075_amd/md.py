@@ -58,6 +58,15 @@ class TBM(C.Structure):
     _fields_ = [("pair", TB * 3)]
 
 
+class TAB(C.Structure):
+    """md_tab_t: knot counts and spacings of a tabulated embedded-atom form."""
+    _fields_ = [("nr", C.c_int32), ("nrho", C.c_int32), ("dr", C.c_double), ("drho", C.c_double)]
+
+
+def tab_params(tab: dict) -> TAB:
+    return TAB(len(tab["psi"]), len(tab["F"]), float(tab["dr"]), float(tab["drho"]))
+
+
 def tbm_params(pairs) -> TBM:
     m = TBM()
     for k in range(3):
@@ -102,10 +111,11 @@ class System(C.Structure):
                 ("force_ms", C.c_double), ("force_calls", C.c_int64),
                 ("mlp", MLP), ("mlp_w", C.c_void_p), ("dEdG", C.c_void_p), ("idx_in", C.c_void_p),
                 ("cnt_in", C.c_void_p), ("tb", TB), ("tbm", TBM), ("types", C.c_void_p),
-                ("types_scratch", C.c_void_p)]
+                ("types_scratch", C.c_void_p), ("tab", TAB), ("tab_table", C.c_void_p)]
 
 
-MD_POT_LJ, MD_POT_EAM, MD_POT_MLP, MD_POT_TB, MD_POT_TBM = 0, 1, 2, 3, 4
+MD_POT_LJ, MD_POT_EAM, MD_POT_MLP, MD_POT_TB, MD_POT_TBM, MD_POT_TAB = 0, 1, 2, 3, 4, 5
+MD_TAB_MAX_KNOTS = 2001
 
 
 class MDError(RuntimeError):
@@ -146,6 +156,11 @@ def lib():
         L.md_forces_tbm.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(TBM), _vp,
                                     _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
         L.md_set_elements.argtypes = [C.c_int64, _vp, _vp, _vp]
+        L.md_tab_bytes.argtypes = [C.POINTER(TAB)]
+        L.md_tab_bytes.restype = C.c_int64
+        L.md_tab_pack.argtypes = [C.POINTER(TAB), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.md_forces_tab.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(TAB), _vp,
+                                    _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
         L.md_mlp_descriptors.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(MLP),
                                          _vp, _vp]
         L.md_mlp_eval.argtypes = [C.c_int64, _vp, C.POINTER(MLP), _vp, _vp, _vp, _vp]
@@ -333,6 +348,38 @@ def md_set_elements(n: int, types, xs, stream=None):
     import torch
     _check(lib().md_set_elements(int(n), _ptr(types, torch.int32, n, "types"), _ptr(xs, torch.int32, 4 * n, "xs"),
                                  _stream(stream)), "md_set_elements")
+
+
+def md_tab_bytes(tab: dict) -> int:
+    return int(lib().md_tab_bytes(C.byref(tab_params(tab))))
+
+
+def md_tab_pack(tab: dict, table, stream=None):
+    """Fill the device table (uint8 tensor of md_tab_bytes bytes) from the
+    host knot arrays of `tab` (dict with dr, drho, psi, dpsi, phi, dphi, F,
+    dF)."""
+    import numpy as np
+    import torch
+    t = tab_params(tab)
+    arrs = [np.ascontiguousarray(tab[k], dtype=np.float64) for k in ("psi", "dpsi", "phi", "dphi", "F", "dF")]
+    if any(len(a) != t.nr for a in arrs[:4]) or any(len(a) != t.nrho for a in arrs[4:]):
+        raise ValueError("knot arrays of unequal length")
+    _check(lib().md_tab_pack(C.byref(t), *[a.ctypes.data_as(_vp) for a in arrs],
+                             _ptr(table, torch.uint8, md_tab_bytes(tab), "table"), _stream(stream)), "md_tab_pack")
+
+
+def md_forces_tab(L, n: int, xs, row_cap: int, idx, count, tab: dict, table, rho, fprime, f, ev, flags: int, ws,
+                  stream=None, e_atom=None):
+    import torch
+    t = tab_params(tab)
+    _check(lib().md_forces_tab(C.byref(box(L)), int(n), _ptr(xs, torch.int32, 4 * n, "xs"), int(row_cap),
+                               _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"),
+                               _ptr(count, torch.int32, n, "count"), C.byref(t),
+                               _ptr(table, torch.uint8, md_tab_bytes(tab), "table"),
+                               _ptr(rho, torch.float32, n, "rho"), _ptr(fprime, torch.float32, n, "fprime"),
+                               _ptr(f, torch.float32, 3 * n, "f"), _ptr(e_atom, torch.float32, n, "e_atom"),
+                               _ptr(ev, torch.float64, 8, "ev"), int(flags), _ptr(ws, name="ws"), ws.numel(),
+                               _stream(stream)), "md_forces_tab")
 
 
 def md_mlp_descriptors(L, n: int, xs, row_cap: int, idx, count, mlp: MLP, G, stream=None):

@@ -26,7 +26,9 @@ class Simulation:
     potential: "lj" (params eps, sigma, rc), "eam" (Finnis-Sinclair dict),
     "tb" (second-moment tight-binding dict: A, xi, p, q, r0, rs, rc), "tbm"
     (two elements: `tbm` = three such dicts for the pair kinds 0-0, 0-1, 1-1,
-    `types` = the element 0/1 of each input atom) or
+    `types` = the element 0/1 of each input atom), "tab" (tabulated
+    embedded-atom functions: dict with dr, drho and the knot arrays psi,
+    dpsi, phi, dphi, F, dF) or
     "mlp" (descriptor geometry and normalisation `mlp`, an md.MLP, and the
     MD_MLP_NPARAM bfloat16 parameters `mlp_w`, an int16 device tensor).
     Positions and velocities are FP64; forces FP32 (FP64 with pair_fp64).
@@ -34,7 +36,7 @@ class Simulation:
     """
 
     def __init__(self, L, x, v, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None, tb=None, tbm=None, types=None,
-                 mlp=None, mlp_w=None,
+                 tab=None, mlp=None, mlp_w=None,
                  skin=0.3, dt=0.005, mass=1.0, force_to_accel=1.0, reach=1, pair_fp64=False,
                  compensate=True, device="cuda", row_cap=None, list_slack=1.2):
         self.L = np.asarray(L, dtype=np.float64).reshape(3)
@@ -45,6 +47,8 @@ class Simulation:
         self.fs = fs
         self.tb = tb
         self.tbm = tbm
+        self.tab = tab
+        self.tab_table = None
         self.mlp, self.mlp_w = mlp, mlp_w
         if potential == "lj":
             rc = self.lj[2]
@@ -56,6 +60,10 @@ class Simulation:
             if tbm is None or types is None:
                 raise ValueError("potential 'tbm' needs tbm and types")
             rc = max(float(t["rc"]) for t in tbm)
+        elif potential == "tab":
+            if tab is None:
+                raise ValueError("potential 'tab' needs tab")
+            rc = (len(tab["psi"]) - 1) * float(tab["dr"])
         elif potential == "mlp":
             if mlp is None or mlp_w is None:
                 raise ValueError("potential 'mlp' needs mlp and mlp_w")
@@ -90,6 +98,9 @@ class Simulation:
             if self.types.numel() != n:
                 raise ValueError("types needs one element per atom")
             self._types2 = torch.empty_like(self.types)
+        if potential == "tab":
+            self.tab_table = torch.empty(M.md_tab_bytes(tab), dtype=torch.uint8, device=d)
+            M.md_tab_pack(tab, self.tab_table)
         self.xs = torch.zeros((max(n, 1), 4), dtype=torch.int32, device=d)
         fdt = torch.float64 if pair_fp64 else torch.float32
         self.f = torch.zeros((3, max(n, 1)), dtype=fdt, device=d)
@@ -187,6 +198,9 @@ class Simulation:
         elif self.potential == "tbm":
             M.md_forces_tbm(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.tbm, self.rho,
                             self.fprime, self.f, self.ev, fl, self.ws, e_atom=ea)
+        elif self.potential == "tab":
+            M.md_forces_tab(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.tab, self.tab_table,
+                            self.rho, self.fprime, self.f, self.ev, fl, self.ws, e_atom=ea)
         else:
             M.md_forces_mlp(self.L, self.n, self.xs, self.row_cap, self.idx, self.count, self.mlp, self.mlp_w,
                             self.dEdG, self.idx_in, self.cnt_in, ea, self.f, self.ev, fl, self.ws)
@@ -270,8 +284,10 @@ class Simulation:
         if self.tbm is not None:
             S.tbm = M.tbm_params(self.tbm)
             S.types, S.types_scratch = ptr(self.types), ptr(self._types2)
+        if self.tab is not None:
+            S.tab, S.tab_table = M.tab_params(self.tab), ptr(self.tab_table)
         S.potential = {"lj": M.MD_POT_LJ, "eam": M.MD_POT_EAM, "mlp": M.MD_POT_MLP,
-                       "tb": M.MD_POT_TB, "tbm": M.MD_POT_TBM}[self.potential]
+                       "tb": M.MD_POT_TB, "tbm": M.MD_POT_TBM, "tab": M.MD_POT_TAB}[self.potential]
         if self.potential == "mlp":
             S.mlp, S.mlp_w, S.dEdG = self.mlp, ptr(self.mlp_w), ptr(self.dEdG)
             S.idx_in, S.cnt_in = ptr(self.idx_in), ptr(self.cnt_in)

@@ -55,6 +55,17 @@ def test_host_only_entry_points(lib):
     assert "neighbour" in md.error_string(md.MD_ERR_CAPACITY)
 
 
+def test_tab_bytes_host_only(lib):
+    from paper_1611_00075_amd import inputs, md
+    tab = inputs.fs_table(inputs.FS_CU)
+    nr, nrho = len(tab["psi"]), len(tab["F"])
+    assert md.md_tab_bytes(tab) == 32 * (nr - 1) + 16 * (nrho - 1)
+    assert md.md_tab_bytes(dict(tab, psi=np.zeros(md.MD_TAB_MAX_KNOTS + 1))) == 0
+    assert md.md_tab_bytes(dict(tab, psi=np.zeros(1))) == 0
+    assert md.md_tab_bytes(dict(tab, dr=0.0)) == 0
+    assert md.md_tab_bytes(dict(tab, drho=float("nan"))) == 0
+
+
 def _morton(x, y, z):
     c = 0
     for b in range(21):
