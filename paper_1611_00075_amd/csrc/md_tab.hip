@@ -13,10 +13,12 @@
 // pair forces gathering F'), with one difference: the r tables live in LDS,
 // where a lane's lookup is one 16-byte LDS read instead of a second
 // scattered global gather beside the neighbour's position.  Staging a table
-// per block only pays when a block covers many atoms, so these kernels run
-// a persistent grid (as many blocks as fit on the device, 8 waves each
-// sharing one copy of the table); each wave walks whole slices of 8 atoms,
-// the slices of one XCD forming one contiguous Morton range.
+// per block only pays when a block covers many atoms, so the blocks are
+// large (16 waves sharing one copy of the table) and each covers a
+// contiguous run of slices of 8 atoms, the runs of one XCD forming one
+// contiguous Morton range.  The grid is a few times what is resident at
+// once: with exactly one resident round the slowest waves set the time;
+// with several, the dispatcher fills the CUs that finish first.
 #include <cmath>
 #include <type_traits>
 #include <vector>
@@ -25,7 +27,8 @@
 
 namespace md {
 
-constexpr int kTabBlock = 512;
+constexpr int kTabBlock = 1024;
+constexpr uint32_t kTabRounds = 4;   // grid = this many times the resident blocks
 constexpr int kTabWaves = kTabBlock / kWave;
 
 struct TAB32 {
@@ -75,9 +78,10 @@ __device__ __forceinline__ void tab_embed(const TAB32 &p, const float4 *__restri
     Fp = d * p.inv_drho;
 }
 
-// The slices of this wave: one contiguous range per XCD, interleaved over
-// the waves of the blocks on that XCD (block b runs on XCD b % 8; the grid
-// is a multiple of 8 blocks).
+// The slices of this wave: XCD x (block b runs on XCD b % 8; the grid is a
+// multiple of 8 blocks) owns one contiguous range of slices, cut into one
+// contiguous run per block of that XCD; the waves of a block interleave
+// over its run.
 struct SliceRange {
     uint32_t first, end, stride;
 };
@@ -89,7 +93,9 @@ __device__ __forceinline__ SliceRange wave_slices(uint32_t nslices)
     const uint32_t chunk = (nslices + kXcds - 1) / kXcds;
     const uint32_t lo = x * chunk;
     const uint32_t hi = min(lo + chunk, nslices);
-    return {lo + (blockIdx.x / kXcds) * kTabWaves + wave, hi, per_xcd * kTabWaves};
+    const uint32_t run = (chunk + per_xcd - 1) / per_xcd;
+    const uint32_t b0 = lo + (blockIdx.x / kXcds) * run;
+    return {b0 + wave, min(b0 + run, hi), uint32_t(kTabWaves)};
 }
 
 // Sum of NV doubles over the block's waves, fixed order; valid in thread 0.
@@ -307,8 +313,9 @@ int tab_pack(const md_tab_t *t, const double *psi, const double *dpsi, const dou
     return MD_OK;
 }
 
-// Blocks of the persistent grid: as many as fit on the device at once for
-// this kernel and LDS size, a multiple of 8, no more than the slices need.
+// Blocks of the grid: kTabRounds times as many as fit on the device at once
+// for this kernel and LDS size, a multiple of 8, no more than the slices
+// need.
 static uint32_t tab_grid(const void *kernel, size_t lds, uint32_t nslices)
 {
     static int cus[64] = {0};
@@ -322,7 +329,7 @@ static uint32_t tab_grid(const void *kernel, size_t lds, uint32_t nslices)
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kTabBlock, lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    const uint32_t full = uint32_t(cus[dev]) * uint32_t(per_cu);
+    const uint32_t full = uint32_t(cus[dev]) * uint32_t(per_cu) * kTabRounds;
     const uint32_t need = (nslices + kTabWaves - 1) / kTabWaves;
     const uint32_t g = need < full ? need : full;
     return (g + kXcds - 1) / kXcds * kXcds;
