@@ -374,6 +374,28 @@ def main():
         }
         del sim5, s5
         torch.cuda.empty_cache()
+        # ---- tabulated functions (the FS set sampled at dr = 0.005 A), 4 M atoms
+        log("tabulated crystal: generating")
+        s7 = inputs.eam_cu()
+        tab7 = inputs.fs_table(inputs.FS_CU)
+        sim7 = Simulation(s7.L, s7.x, s7.v, potential="tab", tab=tab7, skin=1.0, dt=1.0, mass=inputs.CU_MASS_AMU,
+                          force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
+        log("tabulated crystal: running")
+        r7 = run_workload(sim7, 200, 10, torch)
+        f7 = r7["force_ms"]
+        b7 = eam_force_bytes(s7.n, sim7.n_pairs)
+        extra["tab_cu_fcc_100^3"] = {
+            "atoms": s7.n, "steps": 200, "value": s7.n * 200 / r7["seconds"], "unit": "atom-steps/s",
+            "ms_per_step": 1e3 * r7["seconds"] / 200, "rebuilds": r7["rebuilds"], "list_entries": sim7.n_pairs,
+            "forces_ms": f7, "forces_GBs": b7 / (f7 * 1e-3) / 1e9,
+            "forces_frac_hbm": b7 / (f7 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "forces_frac_copy": b7 / (f7 * 1e-3) / 1e9 / copy_gbs,
+            "potential": "tabulated psi, Phi, F (cubic Hermite between knots) sampled from the FS set: "
+                         f"{len(tab7['psi'])} r knots at 0.005 A, {len(tab7['F'])} rho knots; list 5.4 A",
+            "phases_ms_per_call_api": {k: v[0] for k, v in r7["phases"].items()},
+        }
+        del sim7, s7
+        torch.cuda.empty_cache()
         # ---- two elements: random alloy and two layers, 4 M atoms ---------
         for layered in (False, True):
             name = "tbm_cu_au_layers_100^3" if layered else "tbm_cu75au25_alloy_100^3"

@@ -123,6 +123,29 @@ def test_tb_full_size(M, orc):
     _check_fp32(np.concatenate(fg_all), np.concatenate(fo_all), "TB Cu 4M")
 
 
+def test_tab_full_size(M, orc):
+    """The 4 M-atom Cu crystal with the tabulated form (the FS set sampled at
+    dr = 0.005 A) after 20 driver steps, against the oracle on the same
+    tables."""
+    tab = inputs.fs_table(inputs.FS_CU)
+    rc = (len(tab["psi"]) - 1) * tab["dr"]
+    s = inputs.eam_cu()
+    from paper_1611_00075_amd.sim import Simulation
+    sim = Simulation(s.L, s.x, s.v, potential="tab", tab=tab, skin=1.0, dt=1.0, mass=inputs.CU_MASS_AMU,
+                     force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
+    sim.run(20)
+    x, fg = sim.positions(), sim.forces().astype(np.float64)
+    del sim
+    torch.cuda.empty_cache()
+    fo_all, fg_all = [], []
+    for pos, Lb, core, sel in _regions(x, s.L, _centres(x, 3, 5), 8.0, 2 * rc + 0.5, rc + 1.0):
+        off, idx = orc.neighbors_brute(pos, Lb, rc + 1.0)
+        fo = orc.forces_tab(pos, Lb, off, idx, tab)["f"]
+        fo_all.append(fo[core])
+        fg_all.append(fg[sel[core]])
+    _check_fp32(np.concatenate(fg_all), np.concatenate(fo_all), "tabulated Cu 4M")
+
+
 def test_mlp_full_size(M, orc):
     """MLP forces of the 4 M-atom crystal (thermalised by 20 EAM steps),
     random BF16 network."""
