@@ -54,6 +54,12 @@ def recorded_traffic(key):
     return rec["traffic_bytes"]
 
 
+def recorded_pair(k1, k2):
+    """Recorded traffic of a two-pass force evaluation (both passes), or None."""
+    a, b = recorded_traffic(k1), recorded_traffic(k2)
+    return None if a is None or b is None else a + b
+
+
 def log(msg):
     """Progress line on stderr (the JSON result goes to stdout)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -345,6 +351,8 @@ def main():
                 "forces_ms": f3, "forces_GBs": b3 / (f3 * 1e-3) / 1e9,
                 "forces_frac_hbm": b3 / (f3 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "forces_frac_copy": b3 / (f3 * 1e-3) / 1e9 / copy_gbs,
+                "forces_traffic_bytes": recorded_pair("k_eam_rho_cu_4M", "k_eam_force_cu_4M"),
+                "forces_bytes": b3,
                 "phases_ms_per_call_api": {k: v[0] for k, v in r3["phases"].items()},
             }
         _, ke3 = sim3.energies()
@@ -368,6 +376,7 @@ def main():
             "forces_ms": f5, "forces_GBs": b5 / (f5 * 1e-3) / 1e9,
             "forces_frac_hbm": b5 / (f5 * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "forces_frac_copy": b5 / (f5 * 1e-3) / 1e9 / copy_gbs,
+            "forces_traffic_bytes": recorded_pair("k_tb_rho_cu_4M", "k_tb_force_cu_4M"), "forces_bytes": b5,
             "potential": "second-moment tight-binding (exponential psi and Phi, sqrt embedding), "
                          "synthetic Cu-like parameters, rc 5.0 A, list 6.0 A",
             "phases_ms_per_call_api": {k: v[0] for k, v in r5["phases"].items()},
@@ -390,6 +399,7 @@ def main():
             "forces_ms": f7, "forces_GBs": b7 / (f7 * 1e-3) / 1e9,
             "forces_frac_hbm": b7 / (f7 * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "forces_frac_copy": b7 / (f7 * 1e-3) / 1e9 / copy_gbs,
+            "forces_traffic_bytes": recorded_pair("k_tab_rho_cu_4M", "k_tab_force_cu_4M"), "forces_bytes": b7,
             "potential": "tabulated psi, Phi, F (cubic Hermite between knots) sampled from the FS set: "
                          f"{len(tab7['psi'])} r knots at 0.005 A, {len(tab7['F'])} rho knots; list 5.4 A",
             "phases_ms_per_call_api": {k: v[0] for k, v in r7["phases"].items()},
@@ -415,6 +425,8 @@ def main():
                 "forces_ms": f6, "forces_GBs": b6 / (f6 * 1e-3) / 1e9,
                 "forces_frac_hbm": b6 / (f6 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "forces_frac_copy": b6 / (f6 * 1e-3) / 1e9 / copy_gbs,
+                "forces_traffic_bytes": recorded_pair("k_tbm_rho_cu_au_4M", "k_tbm_force_cu_au_4M"),
+                "forces_bytes": b6,
                 "phases_ms_per_call_api": {k: v[0] for k, v in r6["phases"].items()},
             }
             del sim6, s6
