@@ -421,6 +421,128 @@ int md_mlp_train_step(int64_t batch, const int32_t *sel, const float *G,
                       float *m2, uint16_t *w, double *loss, void *tws,
                       size_t tws_bytes, void *stream);
 
+/* ---- domain decomposition on one device ----
+ *
+ * Sec. 2.1's spatial decomposition with the asynchronous force step of its
+ * hybrid algorithm (pack the boundary coordinates, send, receive, forces
+ * inside the domain while the messages travel, wait, forces across the
+ * domain boundary), for the LJ and FS forms.  The periodic box is cut into
+ * p[0] x p[1] x p[2] equal bricks, all on this device (each the share one
+ * device of a multi-device run would hold).  Each brick holds its own
+ * atoms and ghost copies of the atoms of the neighbouring bricks (periodic
+ * images included) within one halo layer of width c >= r_list of its
+ * faces.  A brick is computed in its own frame, a periodic box of k+3
+ * cells of edge c per axis (c = brick edge / k): cells 1..k cover the
+ * brick, cells 0 and k+1 the halo, cell k+2 is an empty gap so that no pair
+ * forms across the frame's periodic boundary.  Cells are ranked inner cells
+ * first (at least one cell inside the brick faces), then the brick's face
+ * layer (outer cells), then ghost cells, so a brick's sorted atoms are its
+ * inner atoms (no ghost within r_list at a build), its outer atoms, and
+ * its ghosts.
+ *
+ * State after md_dd_rebuild: the atoms in x, v, ids are grouped by brick
+ * (brick t holds [brick_start[t], brick_start[t+1]), in its sorted order);
+ * brick t's atoms and ghosts own the slots [slot0[t], slot0[t] + n_t + g_t)
+ * of xs, count, and of the sliced-ELL list (at idx + slot0[t] * row_cap);
+ * ghost entry k (k < n_ghost, grouped by brick) is a copy of atom
+ * gh_src[k] in slot gh_slot[k]. */
+#define MD_DD_MAX_BRICKS 64
+
+typedef struct md_dd {
+    /* geometry: md_dd_init */
+    md_box_t box;                /* the periodic box */
+    int32_t p[3];                /* bricks per axis, >= 1 */
+    int32_t n_bricks;
+    int32_t k[3];                /* cells per brick edge, >= 3 */
+    double c[3];                 /* cell edge (halo width), >= r_list */
+    md_box_t vbox;               /* a brick's frame: (k + 3) c per axis */
+    md_grid_t vgrid;             /* its cells */
+    int64_t inner_cells;         /* cells ranked first */
+    /* set by the caller */
+    int32_t potential;           /* MD_POT_LJ or MD_POT_EAM */
+    int32_t flags;               /* MD_NO_COMPENSATE */
+    md_lj_t lj;
+    md_fs_t fs;
+    int64_t n;                   /* atoms */
+    double *x, *v, *xref;        /* device [3][n] */
+    int32_t *ids;                /* device [n] */
+    double *x2, *v2;             /* device [3][n] scratch */
+    int32_t *ids2;               /* device [n] scratch */
+    float *f;                    /* device [3][n] */
+    float *rho, *fprime;         /* device [n] (MD_POT_EAM) */
+    int32_t row_cap;             /* list row capacity (multiple of 8) */
+    int64_t slot_cap;            /* capacity of xs, count (slots) */
+    uint32_t *xs;                /* device [slot_cap][4] */
+    int32_t *count;              /* device [slot_cap] */
+    int32_t *idx;                /* device [slot_cap * row_cap] */
+    int64_t ghost_cap;           /* capacity of the ghost entry arrays */
+    int32_t *gh_src, *gh_slot, *gh_code, *gh_src_slot;   /* device [ghost_cap] */
+    double *send, *recv;         /* device [3 * ghost_cap] */
+    uint32_t *send_w, *recv_w;   /* device [ghost_cap] */
+    void *vws;                   /* workspace of vgrid for slot_cap atoms (md_dd_workspace_init) */
+    size_t vws_bytes;
+    void *dws;                   /* scratch of md_dd_scratch_bytes */
+    size_t dws_bytes;
+    int32_t *status;             /* device int32[2], zero-initialised */
+    /* set by md_dd_rebuild */
+    int64_t n_ghost;
+    int64_t brick_start[MD_DD_MAX_BRICKS + 1];
+    int64_t slot0[MD_DD_MAX_BRICKS + 1];
+    int64_t ghost_start[MD_DD_MAX_BRICKS + 1];
+    int64_t n_inner[MD_DD_MAX_BRICKS];   /* atoms in inner cells per brick */
+    int64_t ghost_needed, slot_needed;   /* out: set with MD_ERR_CAPACITY */
+    int32_t row_cap_needed;
+    int32_t phase;               /* md_dd_run: 0 at a step boundary; 1 forces and
+                                    the closing kick pending; 2 a build first */
+    int64_t builds, steps;
+    void *events[4];             /* created on first use, md_dd_release */
+} md_dd_t;
+
+/* Host only.  Fills the geometry of *dd (box, p, n_bricks, k, c, vbox,
+ * vgrid, inner_cells) for lists of cutoff r_list: k[a] =
+ * floor(brick edge / (r_list (1 + 1e-6))), which must be >= 3.
+ * MD_ERR_BOX otherwise or for more than MD_DD_MAX_BRICKS bricks. */
+int md_dd_init(md_dd_t *dd, const md_box_t *box, const int32_t p[3],
+               double r_list);
+
+/* Host only.  Bytes of dws for dd->n, dd->ghost_cap, dd->slot_cap. */
+size_t md_dd_scratch_bytes(const md_dd_t *dd);
+
+/* Uploads the cell ranks of dd->vgrid (inner, outer, ghost classes, Morton
+ * order inside each) into dd->vws (md_workspace_bytes(&dd->vgrid,
+ * dd->slot_cap) bytes) and the frame offsets into dd->dws.  Synchronises
+ * `stream`. */
+int md_dd_workspace_init(md_dd_t *dd, void *stream);
+
+/* Wraps the positions, regroups the atoms by brick (stable), selects the
+ * ghosts of every brick, sorts each brick's atoms and ghosts by cell and
+ * builds its lists, orders each brick's atoms as sorted, and sets
+ * xref = x.  Synchronises `stream` (it reads sizes back).
+ * MD_ERR_CAPACITY with ghost_needed, slot_needed or row_cap_needed set when
+ * a buffer is too small (grow it and call again). */
+int md_dd_rebuild(md_dd_t *dd, void *stream);
+
+/* Forces of the current positions in the asynchronous order: local
+ * coordinates scaled into the brick frames, ghost coordinates packed,
+ * copied and unpacked on `comm` while the inner atoms' forces run on
+ * `stream`, then the outer atoms' (FS: both passes so split, with the F'
+ * of ghosts exchanged on `comm` between them).  f, rho, fprime are indexed
+ * like x.  With MD_ENERGY in flags, ev[8] as md_forces_lj / md_forces_eam
+ * over all atoms.  `comm` may equal `stream`. */
+int md_dd_forces(md_dd_t *dd, double *ev, int32_t flags, void *stream,
+                 void *comm);
+
+/* `steps` velocity-Verlet steps (dt, accel as md_integrate) with the
+ * displacement rebuild rule (skin/2) checked after every drift (the flag
+ * is read back each step), md_dd_rebuild when it fires, md_dd_forces.
+ * A build that reports MD_ERR_CAPACITY returns at once with phase = 2:
+ * grow the buffers and call again; the pending step is completed first. */
+int md_dd_run(md_dd_t *dd, int64_t steps, double dt, double accel,
+              double skin, void *stream, void *comm);
+
+/* Destroys the events md_dd_forces created. */
+int md_dd_release(md_dd_t *dd);
+
 /* ---- step a7: velocity Verlet ---- */
 
 #define MD_KICK_DRIFT 1   /* v += dt/2 a f; x += dt v; rebuild check */

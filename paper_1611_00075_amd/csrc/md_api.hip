@@ -153,29 +153,42 @@ size_t md_workspace_bytes(const md_grid_t *grid, int64_t n)
     return ws_layout(grid->n_cells, n).total;
 }
 
-int md_workspace_init(const md_grid_t *grid, int64_t n, void *ws, size_t ws_bytes, void *stream)
+// Cell tables of `grid` under the cell order lin2rank (a permutation of the
+// cells) into a workspace laid out for n atoms, status words cleared;
+// synchronises s.
+extern "C++" int md::workspace_upload(const md_grid_t *grid, int64_t n, const int32_t *l2r, void *ws,
+                                      size_t ws_bytes, hipStream_t s)
 {
-    if (!grid_ok(grid) || n < 0 || n > kMaxAtoms) return MD_ERR_ARG;
     WsLayout w;
     if (int rc = ws_check(grid, n, ws, ws_bytes, w)) return rc;
-    std::vector<int32_t> l2r(size_t(grid->n_cells)), r2l(size_t(grid->n_cells));
-    if (int rc = md_grid_cell_ranks(grid, l2r.data())) return rc;
-    // rank -> packed cell coordinates cx | cy << 10 | cz << 20
     const int64_t nc0 = grid->nc[0], nc1 = grid->nc[1];
+    std::vector<int32_t> r2l(size_t(grid->n_cells), -1);
     for (int64_t l = 0; l < grid->n_cells; ++l) {
+        const int32_t r = l2r[size_t(l)];
+        if (r < 0 || r >= grid->n_cells || r2l[size_t(r)] != -1) return MD_ERR_ARG;
+        // rank -> packed cell coordinates cx | cy << 10 | cz << 20
         const int32_t cx = int32_t(l % nc0), cy = int32_t((l / nc0) % nc1), cz = int32_t(l / (nc0 * nc1));
-        r2l[size_t(l2r[size_t(l)])] = cx | (cy << 10) | (cz << 20);
+        r2l[size_t(r)] = cx | (cy << 10) | (cz << 20);
     }
     int32_t hdr[64] = {};
     hdr[0] = kWsMagic;
     hdr[1] = int32_t(uint32_t(uint64_t(grid->n_cells) & 0xffffffffu));
     hdr[2] = int32_t(uint32_t(uint64_t(grid->n_cells) >> 32));
-    hipStream_t s = as_stream(stream);
-    MD_HIP_TRY(hipMemcpyAsync(ws_ptr<char>(ws, w.lin2rank), l2r.data(), l2r.size() * 4, hipMemcpyHostToDevice, s));
+    MD_HIP_TRY(hipMemcpyAsync(ws_ptr<char>(ws, w.lin2rank), l2r, size_t(grid->n_cells) * 4, hipMemcpyHostToDevice, s));
     MD_HIP_TRY(hipMemcpyAsync(ws_ptr<char>(ws, w.rank2lin), r2l.data(), r2l.size() * 4, hipMemcpyHostToDevice, s));
     MD_HIP_TRY(hipMemcpyAsync(ws_ptr<char>(ws, w.status), hdr, sizeof(hdr), hipMemcpyHostToDevice, s));
     MD_HIP_TRY(hipStreamSynchronize(s));
     return MD_OK;
+}
+
+int md_workspace_init(const md_grid_t *grid, int64_t n, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!grid_ok(grid) || n < 0 || n > kMaxAtoms) return MD_ERR_ARG;
+    WsLayout w;
+    if (int rc = ws_check(grid, n, ws, ws_bytes, w)) return rc;
+    std::vector<int32_t> l2r(size_t(grid->n_cells));
+    if (int rc = md_grid_cell_ranks(grid, l2r.data())) return rc;
+    return workspace_upload(grid, n, l2r.data(), ws, ws_bytes, as_stream(stream));
 }
 
 int md_bin_cells(const md_grid_t *grid, int64_t n, double *x, int32_t *cell, int32_t *perm, int32_t *cell_start,

@@ -159,6 +159,13 @@ int forces_tbm(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, 
                float *, float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t,
                Gate = {});
 int set_elements(int64_t, const int32_t *, uint32_t *, hipStream_t);
+int workspace_upload(const md_grid_t *, int64_t, const int32_t *, void *, size_t, hipStream_t);
+struct Span;
+int span_forces_lj(const md_box_t *, int64_t, const Span &, const uint32_t *, int32_t, const int32_t *,
+                   const int32_t *, const md_lj_t *, float *, int32_t, double *, int64_t *, hipStream_t, Gate = {});
+int span_forces_eam(int, const md_box_t *, int64_t, const Span &, uint32_t *, int32_t, const int32_t *,
+                    const int32_t *, const md_fs_t *, float *, float *, float *, int32_t, double *, int64_t *,
+                    hipStream_t, Gate = {});
 bool tab_ok(const md_tab_t *);
 int64_t tab_bytes(const md_tab_t *);
 int tab_pack(const md_tab_t *, const double *, const double *, const double *, const double *, const double *,

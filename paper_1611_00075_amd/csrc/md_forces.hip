@@ -43,16 +43,16 @@ template <int TPA, int U, bool CUBIC, bool ENERGY, bool COMP>
 __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restrict__ xs,
                                                  int32_t cap, const int32_t *__restrict__ idx,
                                                  const int32_t *__restrict__ count, LJ32 p, float *__restrict__ f,
-                                                 double *__restrict__ part)
+                                                 double *__restrict__ part, Span sp)
 {
     if (gated(p.gate)) return;
     static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const SliceLane sl = slice_lane(blk);
+    const SliceLane sl = slice_lane(blk, sp.slice0);
     const int64_t i = sl.i;
     const int sub = sl.sub;
 
-    const SliceBufs b = slice_bufs(xs, n, idx, cap, blk);
+    const SliceBufs b = slice_bufs(xs, sp.n_xs, idx, cap, blk, sp.slice0);
     float fx = 0.f, fy = 0.f, fz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     double e = 0.0, np = 0.0, w[6] = {0, 0, 0, 0, 0, 0};
     if (i < n) {
@@ -90,8 +90,8 @@ __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restr
     const double gx = combine(fx, cx), gy = combine(fy, cy), gz = combine(fz, cz);
     if (sub == 0 && i < n) {
         f[i] = float(gx);
-        f[n + i] = float(gy);
-        f[2 * n + i] = float(gz);
+        f[sp.fs + i] = float(gy);
+        f[2 * sp.fs + i] = float(gz);
     }
     if (ENERGY) {
         __shared__ double lds[8 * (kBlock / kWave)];
@@ -360,16 +360,16 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
                                                     int32_t cap, const int32_t *__restrict__ idx,
                                                     const int32_t *__restrict__ count, P p,
                                                     float *__restrict__ rho, float *__restrict__ fprime,
-                                                    double *__restrict__ part)
+                                                    double *__restrict__ part, Span sp)
 {
     if (gated(p.gate)) return;
     static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const SliceLane sl = slice_lane(blk);
+    const SliceLane sl = slice_lane(blk, sp.slice0);
     const int64_t i = sl.i;
     const int sub = sl.sub;
 
-    const SliceBufs b = slice_bufs(xs, n, idx, cap, blk);
+    const SliceBufs b = slice_bufs(xs, sp.n_xs, idx, cap, blk, sp.slice0);
     float s = 0.f, c = 0.f;
     uint32_t wi = 0;
     if (i < n) {
@@ -420,16 +420,16 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
                                                       int32_t cap, const int32_t *__restrict__ idx,
                                                       const int32_t *__restrict__ count, P p,
                                                       const float *__restrict__ rho, float *__restrict__ f,
-                                                      float *__restrict__ e_atom, double *__restrict__ part)
+                                                      float *__restrict__ e_atom, double *__restrict__ part, Span sp)
 {
     if (gated(p.gate)) return;
     static_assert(TPA == kSlice, "one slice per wave");
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const SliceLane sl = slice_lane(blk);
+    const SliceLane sl = slice_lane(blk, sp.slice0);
     const int64_t i = sl.i;
     const int sub = sl.sub;
 
-    const SliceBufs b = slice_bufs(xs, n, idx, cap, blk);
+    const SliceBufs b = slice_bufs(xs, sp.n_xs, idx, cap, blk, sp.slice0);
     float fx = 0.f, fy = 0.f, fz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     double e = 0.0, w[6] = {0, 0, 0, 0, 0, 0};
     if (i < n) {
@@ -462,8 +462,8 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
     const double gx = combine(fx, cx), gy = combine(fy, cy), gz = combine(fz, cz);
     if (sub == 0 && i < n) {
         f[i] = float(gx);
-        f[n + i] = float(gy);
-        f[2 * n + i] = float(gz);
+        f[sp.fs + i] = float(gy);
+        f[2 * sp.fs + i] = float(gz);
     }
     if (ENERGY && e_atom) {
         // site energy F(rho_i) + 1/2 sum_j V(r_ij); F as in the first pass
@@ -503,20 +503,45 @@ struct List {
 
 template <int TPA, bool CUBIC, bool E, bool C>
 static void launch_lj32(uint32_t gb, hipStream_t s, int64_t n, const uint4 *q, const List &l, const LJ32 &p,
-                        float *f, double *part)
+                        float *f, double *part, const Span &sp)
 {
     hipLaunchKernelGGL((k_lj32<TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx, l.cnt,
-                       p, f, part);
+                       p, f, part, sp);
 }
 
 template <int TPA, bool CUBIC>
 static void dispatch_lj32(bool e, bool c, uint32_t gb, hipStream_t s, int64_t n, const uint4 *q, const List &l,
-                          const LJ32 &p, float *f, double *part)
+                          const LJ32 &p, float *f, double *part, const Span &sp)
 {
-    if (e && c) launch_lj32<TPA, CUBIC, true, true>(gb, s, n, q, l, p, f, part);
-    else if (e) launch_lj32<TPA, CUBIC, true, false>(gb, s, n, q, l, p, f, part);
-    else if (c) launch_lj32<TPA, CUBIC, false, true>(gb, s, n, q, l, p, f, part);
-    else launch_lj32<TPA, CUBIC, false, false>(gb, s, n, q, l, p, f, part);
+    if (e && c) launch_lj32<TPA, CUBIC, true, true>(gb, s, n, q, l, p, f, part, sp);
+    else if (e) launch_lj32<TPA, CUBIC, true, false>(gb, s, n, q, l, p, f, part, sp);
+    else if (c) launch_lj32<TPA, CUBIC, false, true>(gb, s, n, q, l, p, f, part, sp);
+    else launch_lj32<TPA, CUBIC, false, false>(gb, s, n, q, l, p, f, part, sp);
+}
+
+// blocks of a launch over the slices from sp.slice0 to the one holding atom n-1
+static uint32_t blocks_span(int64_t n, const Span &sp)
+{
+    const int64_t slices = (n + kSlice - 1) / kSlice - int64_t(sp.slice0);
+    return slices > 0 ? uint32_t((slices + kBlock / kWave - 1) / (kBlock / kWave)) : 0u;
+}
+
+static LJ32 lj_constants(const md_box_t *box, const md_lj_t *lj, Gate gate)
+{
+    const double two32 = 4294967296.0;
+    const bool cubic = is_cubic(box);
+    const double u = cubic ? box->L[0] / two32 : 1.0;   // length unit
+    LJ32 p;
+    p.ax = float(box->L[0] / two32);
+    p.ay = float(box->L[1] / two32);
+    p.az = float(box->L[2] / two32);
+    p.len = float(u);
+    p.rc2 = float(lj->rc * lj->rc / (u * u));
+    p.sig2 = float(lj->sigma * lj->sigma / (u * u));
+    p.eps4 = float(4.0 * lj->eps);
+    p.eps24 = float(24.0 * lj->eps / u);
+    p.gate = gate;
+    return p;
 }
 
 int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *xs, int32_t cap, const int32_t *idx,
@@ -557,23 +582,12 @@ int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *x
             const bool cubic = is_cubic(box);
             gb = blocks_for(n, kTPA);
             if (int64_t(gb) > w.red_blocks) return MD_ERR_WORKSPACE;
-            const double two32 = 4294967296.0;
-            const double u = cubic ? box->L[0] / two32 : 1.0;   // length unit
-            LJ32 p;
-            p.ax = float(box->L[0] / two32);
-            p.ay = float(box->L[1] / two32);
-            p.az = float(box->L[2] / two32);
-            p.len = float(u);
-            p.rc2 = float(lj->rc * lj->rc / (u * u));
-            p.sig2 = float(lj->sigma * lj->sigma / (u * u));
-            p.eps4 = float(4.0 * lj->eps);
-            p.eps24 = float(24.0 * lj->eps / u);
-            p.gate = gate;
+            const LJ32 p = lj_constants(box, lj, gate);
             const uint4 *q = reinterpret_cast<const uint4 *>(xs);
             float *ff = static_cast<float *>(f);
             const bool comp = !(flags & MD_NO_COMPENSATE);
-            if (cubic) dispatch_lj32<kTPA, true>(energy, comp, gb, s, n, q, l, p, ff, part);
-            else dispatch_lj32<kTPA, false>(energy, comp, gb, s, n, q, l, p, ff, part);
+            if (cubic) dispatch_lj32<kTPA, true>(energy, comp, gb, s, n, q, l, p, ff, part, whole(n));
+            else dispatch_lj32<kTPA, false>(energy, comp, gb, s, n, q, l, p, ff, part, whole(n));
         }
         MD_HIP_TRY(hipGetLastError());
     }
@@ -582,23 +596,26 @@ int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *x
 }
 
 template <class P, int TPA, bool CUBIC, bool E, bool C>
-static void launch_eam(uint32_t gb, hipStream_t s, int64_t n, uint4 *q, const List &l, const P &p, float *rho,
-                       float *fprime, float *f, float *ea, double *part1, double *part2)
+static void launch_eam(int passes, uint32_t gb, hipStream_t s, int64_t n, uint4 *q, const List &l, const P &p,
+                       float *rho, float *fprime, float *f, float *ea, double *part1, double *part2, const Span &sp)
 {
-    hipLaunchKernelGGL((k_eam_rho<P, TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx,
-                       l.cnt, p, rho, fprime, part1);
-    hipLaunchKernelGGL((k_eam_force<P, TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap,
-                       l.idx, l.cnt, p, rho, f, ea, part2);
+    if (passes & 1)
+        hipLaunchKernelGGL((k_eam_rho<P, TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap,
+                           l.idx, l.cnt, p, rho, fprime, part1, sp);
+    if (passes & 2)
+        hipLaunchKernelGGL((k_eam_force<P, TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap,
+                           l.idx, l.cnt, p, rho, f, ea, part2, sp);
 }
 
 template <class P, int TPA, bool CUBIC>
-static void dispatch_eam(bool e, bool c, uint32_t gb, hipStream_t s, int64_t n, uint4 *q, const List &l,
-                         const P &p, float *rho, float *fprime, float *f, float *ea, double *p1, double *p2)
+static void dispatch_eam(int passes, bool e, bool c, uint32_t gb, hipStream_t s, int64_t n, uint4 *q,
+                         const List &l, const P &p, float *rho, float *fprime, float *f, float *ea, double *p1,
+                         double *p2, const Span &sp)
 {
-    if (e && c) launch_eam<P, TPA, CUBIC, true, true>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
-    else if (e) launch_eam<P, TPA, CUBIC, true, false>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
-    else if (c) launch_eam<P, TPA, CUBIC, false, true>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
-    else launch_eam<P, TPA, CUBIC, false, false>(gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2);
+    if (e && c) launch_eam<P, TPA, CUBIC, true, true>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp);
+    else if (e) launch_eam<P, TPA, CUBIC, true, false>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp);
+    else if (c) launch_eam<P, TPA, CUBIC, false, true>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp);
+    else launch_eam<P, TPA, CUBIC, false, false>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp);
 }
 
 // Both passes of an embedded-atom form P (geometry fields set here).
@@ -616,8 +633,12 @@ static int forces_two_pass(const md_box_t *box, int64_t n, uint32_t *xs, const L
     if (int64_t(gb) > w.red_blocks) return MD_ERR_WORKSPACE;
     uint4 *q = reinterpret_cast<uint4 *>(xs);
     if (n > 0) {
-        if (cubic) dispatch_eam<P, kTPA, true>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, e_atom, part1, part2);
-        else dispatch_eam<P, kTPA, false>(energy, comp, gb, s, n, q, l, p, rho, fprime, f, e_atom, part1, part2);
+        if (cubic)
+            dispatch_eam<P, kTPA, true>(3, energy, comp, gb, s, n, q, l, p, rho, fprime, f, e_atom, part1, part2,
+                                        whole(n));
+        else
+            dispatch_eam<P, kTPA, false>(3, energy, comp, gb, s, n, q, l, p, rho, fprime, f, e_atom, part1, part2,
+                                         whole(n));
         MD_HIP_TRY(hipGetLastError());
     }
     if (energy) return launch_reduce_partials(part1, gb, part2, gb, ev, kReduceEAM, 0.0, 0.0, s);
@@ -627,9 +648,7 @@ static int forces_two_pass(const md_box_t *box, int64_t n, uint32_t *xs, const L
 // displacement unit of the FP32 pair kernels: L/2^32 in a cubic box, else 1
 static double disp_unit(const md_box_t *box) { return is_cubic(box) ? box->L[0] / 4294967296.0 : 1.0; }
 
-int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
-               const md_fs_t *fs, float *rho, float *fprime, float *f, float *e_atom, double *ev, int32_t flags,
-               void *ws, const WsLayout &w, hipStream_t s, Gate gate)
+static FS32 fs_constants(const md_box_t *box, const md_fs_t *fs, Gate gate)
 {
     const double two32 = 4294967296.0;
     const double u = disp_unit(box);
@@ -647,7 +666,15 @@ int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const 
     p.p2 = float(fs->c2);
     p.A = float(fs->A);
     p.gate = gate;
-    return forces_two_pass(box, n, xs, List{cap, idx, cnt}, p, rho, fprime, f, e_atom, ev, flags, ws, w, s);
+    return p;
+}
+
+int forces_eam(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
+               const md_fs_t *fs, float *rho, float *fprime, float *f, float *e_atom, double *ev, int32_t flags,
+               void *ws, const WsLayout &w, hipStream_t s, Gate gate)
+{
+    return forces_two_pass(box, n, xs, List{cap, idx, cnt}, fs_constants(box, fs, gate), rho, fprime, f, e_atom, ev,
+                           flags, ws, w, s);
 }
 
 int forces_tb(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const int32_t *idx, const int32_t *cnt,
@@ -714,6 +741,49 @@ int forces_tbm(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const 
                                ws, w, s);
     return forces_two_pass(box, n, xs, l, tbm_constants<false>(box, tb, gate), rho, fprime, f, e_atom, ev, flags, ws,
                            w, s);
+}
+
+// ---- one range of one brick of a domain decomposition ----
+// Atoms [8 sp.slice0, n) of a brick whose frame box is `vbox`; sp.n_xs
+// atoms (local and ghost) may be gathered.  Partial energy rows (when
+// MD_ENERGY is set) are written from `part` on; *rows gets their number.
+
+int span_forces_lj(const md_box_t *vbox, int64_t n, const Span &sp, const uint32_t *xs, int32_t cap,
+                   const int32_t *idx, const int32_t *cnt, const md_lj_t *lj, float *f, int32_t flags, double *part,
+                   int64_t *rows, hipStream_t s, Gate gate)
+{
+    const uint32_t gb = blocks_span(n, sp);
+    *rows = gb;
+    if (gb == 0) return MD_OK;
+    const LJ32 p = lj_constants(vbox, lj, gate);
+    const List l{cap, idx, cnt};
+    const uint4 *q = reinterpret_cast<const uint4 *>(xs);
+    const bool energy = flags & MD_ENERGY, comp = !(flags & MD_NO_COMPENSATE);
+    if (is_cubic(vbox)) dispatch_lj32<kTPA, true>(energy, comp, gb, s, n, q, l, p, f, part, sp);
+    else dispatch_lj32<kTPA, false>(energy, comp, gb, s, n, q, l, p, f, part, sp);
+    MD_HIP_TRY(hipGetLastError());
+    return MD_OK;
+}
+
+// pass: 1 = densities and F' (rho, fprime, the fourth words), 2 = forces
+int span_forces_eam(int pass, const md_box_t *vbox, int64_t n, const Span &sp, uint32_t *xs, int32_t cap,
+                    const int32_t *idx, const int32_t *cnt, const md_fs_t *fs, float *rho, float *fprime, float *f,
+                    int32_t flags, double *part, int64_t *rows, hipStream_t s, Gate gate)
+{
+    const uint32_t gb = blocks_span(n, sp);
+    *rows = gb;
+    if (gb == 0) return MD_OK;
+    const FS32 p = fs_constants(vbox, fs, gate);
+    const List l{cap, idx, cnt};
+    uint4 *q = reinterpret_cast<uint4 *>(xs);
+    const bool energy = flags & MD_ENERGY, comp = !(flags & MD_NO_COMPENSATE);
+    if (is_cubic(vbox))
+        dispatch_eam<FS32, kTPA, true>(pass, energy, comp, gb, s, n, q, l, p, rho, fprime, f, nullptr, part, part, sp);
+    else
+        dispatch_eam<FS32, kTPA, false>(pass, energy, comp, gb, s, n, q, l, p, rho, fprime, f, nullptr, part, part,
+                                        sp);
+    MD_HIP_TRY(hipGetLastError());
+    return MD_OK;
 }
 
 }  // namespace md

@@ -126,18 +126,31 @@ __device__ __forceinline__ void walk_buf(const __amdgpu_buffer_rsrc_t &xs_r, con
     }
 }
 
-// Buffers of a force kernel's wavefront: the positions (n < 2^28 atoms) and
-// its slice's block of the list.
+// The atoms a force launch covers: the slices from slice0 on, rows and
+// outputs of atoms below n (the kernel's n argument); positions of the
+// first n_xs atoms may be gathered (atoms from n to n_xs are ghost copies
+// whose forces are not computed); force component c of atom i at
+// f[c * fs + i].  Whole-system launches: n_xs = fs = n, slice0 = 0.
+struct Span {
+    int64_t n_xs;
+    int64_t fs;
+    uint32_t slice0;
+};
+
+__host__ __device__ inline Span whole(int64_t n) { return Span{n, n, 0u}; }
+
+// Buffers of a force kernel's wavefront: the positions (n_xs < 2^28 atoms)
+// and its slice's block of the list.
 struct SliceBufs {
     __amdgpu_buffer_rsrc_t xs, row;
 };
 
-__device__ __forceinline__ SliceBufs slice_bufs(const void *xs, int64_t n, const int32_t *idx, int32_t cap,
-                                                uint32_t blk)
+__device__ __forceinline__ SliceBufs slice_bufs(const void *xs, int64_t n_xs, const int32_t *idx, int32_t cap,
+                                                uint32_t blk, uint32_t slice0 = 0)
 {
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int64_t slice = int64_t(blk) * (kBlock / kWave) + wave;
-    return {make_rsrc(xs, uint32_t(n) * 16u), make_rsrc(idx + slice * cap * kSlice, uint32_t(cap) * 32u)};
+    const int64_t slice = int64_t(slice0) + int64_t(blk) * (kBlock / kWave) + wave;
+    return {make_rsrc(xs, uint32_t(n_xs) * 16u), make_rsrc(idx + slice * cap * kSlice, uint32_t(cap) * 32u)};
 }
 
 // The 8 lanes of one atom are consecutive: combine over them in FP64.
@@ -156,9 +169,10 @@ struct SliceLane {
     int sub;
 };
 
-__device__ __forceinline__ SliceLane slice_lane(uint32_t blk)
+__device__ __forceinline__ SliceLane slice_lane(uint32_t blk, uint32_t slice0 = 0)
 {
-    return {int64_t(blk) * (kBlock / kSlice) + threadIdx.x / kSlice, int(threadIdx.x % kSlice)};
+    return {int64_t(slice0) * kSlice + int64_t(blk) * (kBlock / kSlice) + threadIdx.x / kSlice,
+            int(threadIdx.x % kSlice)};
 }
 
 }  // namespace md

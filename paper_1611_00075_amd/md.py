@@ -114,6 +114,27 @@ class System(C.Structure):
                 ("types_scratch", C.c_void_p), ("tab", TAB), ("tab_table", C.c_void_p)]
 
 
+MD_DD_MAX_BRICKS = 64
+
+
+class DD(C.Structure):
+    """md_dd_t: a domain decomposition on one device (include/md.h)."""
+    _vp = C.c_void_p
+    _fields_ = [("box", Box), ("p", C.c_int32 * 3), ("n_bricks", C.c_int32), ("k", C.c_int32 * 3),
+                ("c", C.c_double * 3), ("vbox", Box), ("vgrid", Grid), ("inner_cells", C.c_int64),
+                ("potential", C.c_int32), ("flags", C.c_int32), ("lj", LJ), ("fs", FS), ("n", C.c_int64),
+                ("x", _vp), ("v", _vp), ("xref", _vp), ("ids", _vp), ("x2", _vp), ("v2", _vp), ("ids2", _vp),
+                ("f", _vp), ("rho", _vp), ("fprime", _vp), ("row_cap", C.c_int32), ("slot_cap", C.c_int64),
+                ("xs", _vp), ("count", _vp), ("idx", _vp), ("ghost_cap", C.c_int64), ("gh_src", _vp),
+                ("gh_slot", _vp), ("gh_code", _vp), ("gh_src_slot", _vp), ("send", _vp), ("recv", _vp),
+                ("send_w", _vp), ("recv_w", _vp), ("vws", _vp), ("vws_bytes", C.c_size_t), ("dws", _vp),
+                ("dws_bytes", C.c_size_t), ("status", _vp), ("n_ghost", C.c_int64),
+                ("brick_start", C.c_int64 * (MD_DD_MAX_BRICKS + 1)), ("slot0", C.c_int64 * (MD_DD_MAX_BRICKS + 1)),
+                ("ghost_start", C.c_int64 * (MD_DD_MAX_BRICKS + 1)), ("n_inner", C.c_int64 * MD_DD_MAX_BRICKS),
+                ("ghost_needed", C.c_int64), ("slot_needed", C.c_int64), ("row_cap_needed", C.c_int32),
+                ("phase", C.c_int32), ("builds", C.c_int64), ("steps", C.c_int64), ("events", _vp * 4)]
+
+
 MD_POT_LJ, MD_POT_EAM, MD_POT_MLP, MD_POT_TB, MD_POT_TBM, MD_POT_TAB = 0, 1, 2, 3, 4, 5
 MD_TAB_MAX_KNOTS = 2001
 
@@ -156,6 +177,14 @@ def lib():
         L.md_forces_tbm.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(TBM), _vp,
                                     _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
         L.md_set_elements.argtypes = [C.c_int64, _vp, _vp, _vp]
+        L.md_dd_init.argtypes = [C.POINTER(DD), C.POINTER(Box), _vp, C.c_double]
+        L.md_dd_scratch_bytes.argtypes = [C.POINTER(DD)]
+        L.md_dd_scratch_bytes.restype = C.c_size_t
+        L.md_dd_workspace_init.argtypes = [C.POINTER(DD), _vp]
+        L.md_dd_rebuild.argtypes = [C.POINTER(DD), _vp]
+        L.md_dd_forces.argtypes = [C.POINTER(DD), _vp, C.c_int32, _vp, _vp]
+        L.md_dd_run.argtypes = [C.POINTER(DD), C.c_int64, C.c_double, C.c_double, C.c_double, _vp, _vp]
+        L.md_dd_release.argtypes = [C.POINTER(DD)]
         L.md_tab_bytes.argtypes = [C.POINTER(TAB)]
         L.md_tab_bytes.restype = C.c_int64
         L.md_tab_pack.argtypes = [C.POINTER(TAB), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -348,6 +377,44 @@ def md_set_elements(n: int, types, xs, stream=None):
     import torch
     _check(lib().md_set_elements(int(n), _ptr(types, torch.int32, n, "types"), _ptr(xs, torch.int32, 4 * n, "xs"),
                                  _stream(stream)), "md_set_elements")
+
+
+def md_dd_init(L, p, r_list: float) -> DD:
+    """Geometry of a decomposition of box L into p bricks (host only)."""
+    dd = DD()
+    pv = (C.c_int32 * 3)(*[int(a) for a in p])
+    _check(lib().md_dd_init(C.byref(dd), C.byref(box(L)), C.cast(pv, C.c_void_p), float(r_list)), "md_dd_init")
+    return dd
+
+
+def md_dd_scratch_bytes(dd: DD) -> int:
+    return int(lib().md_dd_scratch_bytes(C.byref(dd)))
+
+
+def md_dd_workspace_init(dd: DD, stream=None):
+    _check(lib().md_dd_workspace_init(C.byref(dd), _stream(stream)), "md_dd_workspace_init")
+
+
+def md_dd_rebuild(dd: DD, stream=None) -> int:
+    """MD_OK, or MD_ERR_CAPACITY with dd.ghost_needed / slot_needed /
+    row_cap_needed set."""
+    return _check(lib().md_dd_rebuild(C.byref(dd), _stream(stream)), "md_dd_rebuild", allow=(MD_ERR_CAPACITY,))
+
+
+def md_dd_forces(dd: DD, ev=None, flags: int = 0, stream=None, comm=None):
+    import torch
+    _check(lib().md_dd_forces(C.byref(dd), _ptr(ev, torch.float64, 8, "ev"), int(flags), _stream(stream),
+                              _stream(comm) if comm is not None else None), "md_dd_forces")
+
+
+def md_dd_run(dd: DD, steps: int, dt: float, accel: float, skin: float, stream=None, comm=None) -> int:
+    return _check(lib().md_dd_run(C.byref(dd), int(steps), float(dt), float(accel), float(skin), _stream(stream),
+                                  _stream(comm) if comm is not None else None), "md_dd_run",
+                  allow=(MD_ERR_CAPACITY,))
+
+
+def md_dd_release(dd: DD):
+    _check(lib().md_dd_release(C.byref(dd)), "md_dd_release")
 
 
 def md_tab_bytes(tab: dict) -> int:
