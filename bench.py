@@ -406,6 +406,41 @@ def main():
         }
         del sim7, s7
         torch.cuda.empty_cache()
+        # ---- domain decomposition on one device (FS, 4 M atoms) --------------
+        from paper_1611_00075_amd.dd import DomainSimulation
+        for pdd in ((1, 1, 1), (2, 2, 2)):
+            name = "dd_fs_cu_100^3_%dx%dx%d" % pdd
+            log(f"{name}: generating")
+            s8 = inputs.eam_cu()
+            sim8 = DomainSimulation(s8.L, s8.x, s8.v, p=pdd, potential="eam", fs=inputs.FS_CU, skin=1.0, dt=1.0,
+                                    mass=inputs.CU_MASS_AMU, force_to_accel=1.0 / inputs.AMU_A2_FS2_IN_EV)
+            log(f"{name}: running")
+            st8 = torch.cuda.current_stream()
+            sim8.run(10)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st8)
+            for _ in range(20):
+                sim8.compute_forces()
+            e1.record(st8)
+            torch.cuda.synchronize()
+            f8 = e0.elapsed_time(e1) / 20
+            b0 = sim8.dd.builds
+            t0 = time.perf_counter()
+            sim8.run(200)
+            torch.cuda.synchronize()
+            sec8 = time.perf_counter() - t0
+            extra[name] = {
+                "atoms": s8.n, "steps": 200, "value": s8.n * 200 / sec8, "unit": "atom-steps/s",
+                "ms_per_step": 1e3 * sec8 / 200, "rebuilds": int(sim8.dd.builds - b0), "bricks": list(pdd),
+                "ghosts": int(sim8.dd.n_ghost), "forces_ms": f8,
+                "note": "forces: local coordinates into the brick frames, halo pack/copy/unpack on a second stream "
+                        "beside the inner atoms' passes, outer atoms after; F' of ghosts exchanged between the "
+                        "passes; the step loop reads the rebuild flag back every step",
+            }
+            sim8.close()
+            del sim8, s8
+            torch.cuda.empty_cache()
         # ---- two elements: random alloy and two layers, 4 M atoms ---------
         for layered in (False, True):
             name = "tbm_cu_au_layers_100^3" if layered else "tbm_cu75au25_alloy_100^3"
