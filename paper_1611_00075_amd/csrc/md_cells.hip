@@ -284,6 +284,7 @@ __device__ __forceinline__ uint32_t nb_home(const NbTile &T, double xi, double y
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+        if (!mk[c]) continue;   // no hit in this chunk (wave-uniform)
         const uint32_t e = __builtin_amdgcn_mbcnt_hi(uint32_t(mk[c] >> 32),
                                                      __builtin_amdgcn_mbcnt_lo(uint32_t(mk[c]), r));
         // entry e of the row at byte (e / 8) * 256 + (e % 8) * 4
