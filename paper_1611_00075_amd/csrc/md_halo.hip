@@ -281,6 +281,45 @@ __global__ __launch_bounds__(kBlock) void k_dd_scale_local(int64_t n, const doub
                                                 to_fixed(x[2 * n + i] + o[2], sc.k[2]), 0u);
 }
 
+// velocity-Verlet kick (hk = the half kicks due, dt/2 or dt, times the
+// acceleration per unit force) and drift, the displacement rebuild check
+// against xref (status[0] = 1), and the new local coordinates written
+// straight into the brick frames (what k_dd_scale_local does)
+struct DdDrift {
+    double hk, dt, hs2, L[3], hL[3];
+};
+
+__global__ __launch_bounds__(kBlock) void k_dd_kick_drift(int64_t n, double *x, double *v, const float *f,
+                                                          const double *xref, int32_t *status, const int64_t *bstart,
+                                                          const int64_t *slot0, int nb, const double *off, Scale sc,
+                                                          DdDrift a, uint4 *xs)
+{
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    bool moved = false, bad = false;
+    if (i < n) {
+        double p[3];
+        double r2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double vc = v[c * n + i] + a.hk * double(f[c * n + i]);
+            v[c * n + i] = vc;
+            p[c] = x[c * n + i] + a.dt * vc;
+            x[c * n + i] = p[c];
+            bad |= !isfinite(p[c]);
+            double d = p[c] - xref[c * n + i];
+            d = d > a.hL[c] ? d - a.L[c] : (d < -a.hL[c] ? d + a.L[c] : d);
+            r2 = c == 0 ? d * d : (c == 1 ? r2 + d * d : r2 + d * d);
+        }
+        moved = r2 > a.hs2;
+        const int b = brick_of(i, bstart, nb);
+        const double *o = off + (b * kDirs + kSelf) * 3;
+        xs[slot0[b] + (i - bstart[b])] = make_uint4(to_fixed(p[0] + o[0], sc.k[0]), to_fixed(p[1] + o[1], sc.k[1]),
+                                                    to_fixed(p[2] + o[2], sc.k[2]), 0u);
+    }
+    if (__ballot(moved) && (threadIdx.x % kWave) == 0) status[0] = 1;
+    if (__ballot(bad) && (threadIdx.x % kWave) == 0) atomicOr(&status[1], 1);
+}
+
 __global__ __launch_bounds__(kBlock) void k_dd_pack(int64_t m, const double *x, int64_t n, const int32_t *src,
                                                     double *send)
 {
@@ -653,7 +692,17 @@ int md_dd_rebuild(md_dd_t *dd, void *stream)
     return MD_OK;
 }
 
+namespace {
+int dd_forces(md_dd_t *dd, double *ev, int32_t flags, void *stream, void *comm, bool scale_local);
+}
+
 int md_dd_forces(md_dd_t *dd, double *ev, int32_t flags, void *stream, void *comm)
+{
+    return dd_forces(dd, ev, flags, stream, comm, true);
+}
+
+namespace {
+int dd_forces(md_dd_t *dd, double *ev, int32_t flags, void *stream, void *comm, bool scale_local)
 {
     if (!dd || dd->n < 1 || !dd->f || (dd->potential != MD_POT_LJ && dd->potential != MD_POT_EAM)) return MD_ERR_ARG;
     if (dd->potential == MD_POT_EAM && (!dd->rho || !dd->fprime)) return MD_ERR_ARG;
@@ -674,10 +723,12 @@ int md_dd_forces(md_dd_t *dd, double *ev, int32_t flags, void *stream, void *com
     uint4 *xs = reinterpret_cast<uint4 *>(dd->xs);
     const int32_t fl = (flags | dd->flags) & (MD_ENERGY | MD_NO_COMPENSATE);
 
-    // local coordinates into the brick frames
-    hipLaunchKernelGGL(k_dd_scale_local, dim3(blocks(n)), dim3(kBlock), 0, s, n, dd->x,
-                       ws_ptr<int64_t>(ws, l.bstart), ws_ptr<int64_t>(ws, l.slot0), P, off, scl, xs);
-    MD_HIP_TRY(hipGetLastError());
+    // local coordinates into the brick frames (unless the drift wrote them)
+    if (scale_local) {
+        hipLaunchKernelGGL(k_dd_scale_local, dim3(blocks(n)), dim3(kBlock), 0, s, n, dd->x,
+                           ws_ptr<int64_t>(ws, l.bstart), ws_ptr<int64_t>(ws, l.slot0), P, off, scl, xs);
+        MD_HIP_TRY(hipGetLastError());
+    }
     MD_HIP_TRY(hipEventRecord(eL, s));
     // halo positions: pack, transfer, unpack on the communication stream
     MD_HIP_TRY(hipStreamWaitEvent(sc, eL, 0));
@@ -757,38 +808,61 @@ int md_dd_forces(md_dd_t *dd, double *ev, int32_t flags, void *stream, void *com
     return MD_OK;
 }
 
+}  // namespace
+
+// Steps with the closing half kick of a step fused into the next step's
+// kick-drift (one kick of dt), which also writes the brick-frame
+// coordinates; the last step's closing kick is applied on return.
 int md_dd_run(md_dd_t *dd, int64_t steps, double dt, double accel, double skin, void *stream, void *comm)
 {
     if (!dd || steps < 0 || !dd->status || !(dt > 0.0) || !(skin > 0.0)) return MD_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (dd->builds < 1) {
         if (int rc = md_dd_rebuild(dd, stream)) return rc;
-        if (int rc = md_dd_forces(dd, nullptr, 0, stream, comm)) return rc;
+        if (int rc = dd_forces(dd, nullptr, 0, stream, comm, true)) return rc;
     }
-    const double hs2 = 0.25 * skin * skin;
+    const DdScratch l = scratch_layout(dd);
+    if (dd->dws_bytes < l.total) return MD_ERR_WORKSPACE;
+    DdDrift a;
+    a.dt = dt;
+    a.hs2 = 0.25 * skin * skin;
+    for (int c = 0; c < 3; ++c) {
+        a.L[c] = dd->box.L[c];
+        a.hL[c] = 0.5 * dd->box.L[c];
+    }
+    const double hk = 0.5 * dt * accel;
+    bool pending = false;   // the closing half kick of the last completed step
     for (int64_t k = 0; k < steps; ++k) {
+        bool scaled = false;
         if (dd->phase == 0) {
             if (int rc = launch_fill_i32(dd->status, 2, 0, s)) return rc;
-            if (int rc = md_integrate(MD_KICK_DRIFT, &dd->box, dd->n, dd->x, dd->v, dd->f, dt, accel, 1.0, dd->xref,
-                                      hs2, dd->status, 1, nullptr, nullptr, 0, dd->vws, dd->vws_bytes, stream))
-                return rc;
+            a.hk = pending ? 2.0 * hk : hk;
+            hipLaunchKernelGGL(k_dd_kick_drift, dim3(blocks(dd->n)), dim3(kBlock), 0, s, dd->n, dd->x, dd->v, dd->f,
+                               dd->xref, dd->status, ws_ptr<int64_t>(dd->dws, l.bstart),
+                               ws_ptr<int64_t>(dd->dws, l.slot0), dd->n_bricks, ws_ptr<double>(dd->dws, l.off),
+                               frame_scale(dd), a, reinterpret_cast<uint4 *>(dd->xs));
+            MD_HIP_TRY(hipGetLastError());
+            pending = false;
             int32_t st[2] = {0, 0};
             MD_HIP_TRY(hipMemcpyAsync(st, dd->status, 8, hipMemcpyDeviceToHost, s));
             MD_HIP_TRY(hipStreamSynchronize(s));
             if (st[1]) return MD_ERR_NONFINITE;
             dd->phase = st[0] ? 2 : 1;
+            scaled = !st[0];
         }
         if (dd->phase == 2) {
             if (int rc = md_dd_rebuild(dd, stream)) return rc;
             dd->phase = 1;
         }
-        if (int rc = md_dd_forces(dd, nullptr, 0, stream, comm)) return rc;
-        if (int rc = md_integrate(MD_KICK, &dd->box, dd->n, dd->x, dd->v, dd->f, dt, accel, 1.0, nullptr, 0.0,
-                                  nullptr, 0, nullptr, nullptr, 0, dd->vws, dd->vws_bytes, stream))
-            return rc;
+        if (int rc = dd_forces(dd, nullptr, 0, stream, comm, !scaled)) return rc;
+        pending = true;
         dd->phase = 0;
         ++dd->steps;
     }
+    if (pending)
+        if (int rc = md_integrate(MD_KICK, &dd->box, dd->n, dd->x, dd->v, dd->f, dt, accel, 1.0, nullptr, 0.0,
+                                  nullptr, 0, nullptr, nullptr, 0, dd->vws, dd->vws_bytes, stream))
+            return rc;
     return MD_OK;
 }
 
