@@ -37,10 +37,11 @@ HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 78.6
 
 
-def recorded_traffic(key):
-    """HBM bytes per launch from the committed rocprofv3 counter runs
-    (profiles/traffic.json), or None when a source of the kernel has changed
-    since the counters were taken."""
+def recorded(key, field="traffic_bytes"):
+    """A figure from the committed rocprofv3 counter runs
+    (profiles/traffic.json: HBM bytes per launch, VALU busy percent, ...),
+    or None when a source of the kernel has changed since the counters
+    were taken."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
@@ -51,7 +52,12 @@ def recorded_traffic(key):
         return None
     if h.hexdigest() != rec["sources_sha256"]:
         return None
-    return rec["traffic_bytes"]
+    return rec.get(field)
+
+
+def recorded_traffic(key):
+    """HBM bytes per launch from the committed counter runs, or None."""
+    return recorded(key, "traffic_bytes")
 
 
 def recorded_pair(k1, k2):
@@ -320,6 +326,7 @@ def main():
             "bound": "hbm", "kernel": "k_lj32 (md_forces_lj)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("k_lj32_lj_voids_1.23M"),
+            "valu_busy_pct": recorded("k_lj32_lj_voids_1.23M", "valu_busy_pct"),
             "bytes_per_launch": byt, "launch_ms": f_ms,
         },
         "phases_ms_per_call_api": {k: v[0] for k, v in r["phases"].items()},
@@ -352,6 +359,8 @@ def main():
                 "forces_frac_hbm": b3 / (f3 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "forces_frac_copy": b3 / (f3 * 1e-3) / 1e9 / copy_gbs,
                 "forces_traffic_bytes": recorded_pair("k_eam_rho_cu_4M", "k_eam_force_cu_4M"),
+                "valu_busy_pct": [recorded("k_eam_rho_cu_4M", "valu_busy_pct"),
+                                  recorded("k_eam_force_cu_4M", "valu_busy_pct")],
                 "forces_bytes": b3,
                 "phases_ms_per_call_api": {k: v[0] for k, v in r3["phases"].items()},
             }
@@ -508,6 +517,8 @@ def main():
             "achieved": fl / (t_ms * 1e-3) / 1e12, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": fl / (t_ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS,
             "traffic": recorded_traffic("k_mlp_force_cu_4M"),
+            "valu_busy_pct": recorded("k_mlp_force_cu_4M", "valu_busy_pct"),
+            "net_mfma_util_pct": recorded("k_mlp_net_cu_4M", "mfma_util_pct"),
             "launch_ms": t_ms,
         }
         extra["mlp_cu_fcc_100^3"] = m

@@ -70,7 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restr
                 const float ir2 = __builtin_amdgcn_rcpf(r2);
                 const float s2 = p.sig2 * ir2;
                 const float s6 = s2 * s2 * s2;
-                float fs = p.eps24 * s6 * __builtin_fmaf(2.f, s6, -1.f) * ir2;
+                // 24 eps s6 (2 s6 - 1) / r^2 with the prefactor folded into the bracket
+                float fs = s6 * __builtin_fmaf(2.f * p.eps24, s6, -p.eps24) * ir2;
                 fs = in ? fs : 0.f;
                 bx = __builtin_fmaf(fs, dx, bx);
                 by = __builtin_fmaf(fs, dy, by);
@@ -195,6 +196,7 @@ struct FS32 {
     float d, c, p0, p1, p2, A;  // physical
     Gate gate;
     static constexpr int kRhoWords = 3;   // words of a neighbour's scaled coordinates pass 1 reads
+    static constexpr bool kMasked = true; // row walk with per-slot selects
 };
 
 // Second-moment tight-binding form: psi = exp2(cq - kq r) S(r),
@@ -210,6 +212,7 @@ struct TB32 {
     float A;                // embedding prefactor (1)
     Gate gate;
     static constexpr int kRhoWords = 3;
+    static constexpr bool kMasked = true;
 };
 
 // Two elements: the tight-binding constants per pair kind k = t_i + t_j
@@ -229,6 +232,7 @@ struct TBM32 {
     float A;                // embedding prefactor (1)
     Gate gate;
     static constexpr int kRhoWords = 4;
+    static constexpr bool kMasked = false;   // the longer pair terms favour fewer selects
 };
 
 // ---- pair terms of the forms ------------------------------------------------
@@ -252,14 +256,15 @@ __device__ __forceinline__ PairOut force_term(const FS32 &p, float r2, bool vali
 {
     const float fsum = __uint_as_float(wi) + __uint_as_float(wj);
     const bool in_d = valid && r2 < p.d2u, in_c = valid && r2 < p.c2u;
-    const float ru = __builtin_amdgcn_sqrtf(r2);
-    const float r = ru * p.len;
+    // one reciprocal square root gives both r and 1/r
+    const float ir = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ir * p.len;
     const float dpsi = in_d ? fsum * 2.f * (r - p.d) : 0.f;
     const float t = r - p.c;
     const float poly = __builtin_fmaf(__builtin_fmaf(p.p2, t, p.p1), t, p.p0);
     const float dpoly = __builtin_fmaf(2.f * p.p2, t, p.p1);
     const float dV = in_c ? t * __builtin_fmaf(t, dpoly, 2.f * poly) : 0.f;
-    float g = -(dpsi + dV) * __builtin_amdgcn_rcpf(ru);
+    float g = -(dpsi + dV) * ir;
     g = in_d || in_c ? g : 0.f;
     return {g, in_c ? t * t * poly : 0.f, in_d || in_c};
 }
@@ -283,7 +288,8 @@ __device__ __forceinline__ float tb_psi(float r, float rs, float iw, float kq, f
     return __builtin_amdgcn_exp2f(__builtin_fmaf(-kq, r, cq)) * S;
 }
 
-__device__ __forceinline__ float2 tb_force(float r, float ru, float fsum, float rs, float iw, float kq, float cq,
+// (ir = 1 / r in the displacement unit)
+__device__ __forceinline__ float2 tb_force(float r, float ir, float fsum, float rs, float iw, float kq, float cq,
                                           float lq, float kp, float cp, float lp)
 {
     float S, dS;
@@ -292,7 +298,7 @@ __device__ __forceinline__ float2 tb_force(float r, float ru, float fsum, float 
     const float ep = __builtin_amdgcn_exp2f(__builtin_fmaf(-kp, r, cp));
     const float dpsi = fsum * eq * __builtin_fmaf(-lq, S, dS);
     const float dPhi = ep * __builtin_fmaf(-lp, S, dS);
-    return make_float2(-(dpsi + dPhi) * __builtin_amdgcn_rcpf(ru), ep * S);
+    return make_float2(-(dpsi + dPhi) * ir, ep * S);
 }
 
 __device__ __forceinline__ float rho_term(const TB32 &p, float r2, bool valid, uint32_t, uint32_t)
@@ -304,9 +310,9 @@ __device__ __forceinline__ float rho_term(const TB32 &p, float r2, bool valid, u
 __device__ __forceinline__ PairOut force_term(const TB32 &p, float r2, bool valid, uint32_t wi, uint32_t wj)
 {
     const bool in = valid && r2 < p.cut2u;
-    const float ru = __builtin_amdgcn_sqrtf(r2);
-    const float2 o = tb_force(ru * p.len, ru, __uint_as_float(wi) + __uint_as_float(wj), p.rs, p.iw, p.kq, p.cq,
-                              p.lq, p.kp, p.cp, p.lp);
+    const float ir = __builtin_amdgcn_rsqf(r2);
+    const float2 o = tb_force(r2 * ir * p.len, ir, __uint_as_float(wi) + __uint_as_float(wj), p.rs, p.iw, p.kq,
+                              p.cq, p.lq, p.kp, p.cp, p.lp);
     return {in ? o.x : 0.f, in ? o.y : 0.f, in};
 }
 
@@ -339,11 +345,11 @@ __device__ __forceinline__ PairOut force_term(const TBM32<CC> &p, float r2, bool
     constexpr float kLn2 = 0.693147180559945309f;
     const uint32_t k = (wi & 1u) + (wj & 1u);
     const bool in = valid && r2 < cut_sel<CC>(p.cut2u, k);
-    const float ru = __builtin_amdgcn_sqrtf(r2);
+    const float ir = __builtin_amdgcn_rsqf(r2);
     const float fsum = __uint_as_float(wi & ~1u) + __uint_as_float(wj & ~1u);
     const float kq = sel3(p.kq, k), kp = sel3(p.kp, k);
-    const float2 o = tb_force(ru * p.len, ru, fsum, cut_sel<CC>(p.rs, k), cut_sel<CC>(p.iw, k), kq, sel3(p.cq, k),
-                              kq * kLn2, kp, sel3(p.cp, k), kp * kLn2);
+    const float2 o = tb_force(r2 * ir * p.len, ir, fsum, cut_sel<CC>(p.rs, k), cut_sel<CC>(p.iw, k), kq,
+                              sel3(p.cq, k), kq * kLn2, kp, sel3(p.cp, k), kp * kLn2);
     return {in ? o.x : 0.f, in ? o.y : 0.f, in};
 }
 
@@ -376,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
         const uint4 pi = xs[i];
         wi = pi.w;
         const int32_t cnt = min(count[i], cap);
-        walk_buf<U, P::kRhoWords>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
+        walk_buf<U, P::kRhoWords, P::kMasked>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
             float bs = 0.f;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -435,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
     if (i < n) {
         const uint4 pi = xs[i];
         const int32_t cnt = min(count[i], cap);
-        walk_buf<U, 4>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
+        walk_buf<U, 4, P::kMasked>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
             float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll
             for (int u = 0; u < U; ++u) {

@@ -96,7 +96,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
 // body(pj, t) with the U positions of entries t + 8 u.  For entries past
 // the row end both loads are given an offset outside their buffer, so they
 // move no data and return zero; the body masks them (t + 8 u >= cnt).
-template <int U, int WORDS, typename Body>
+//
+// MASKED = false drops the two per-slot selects: slots past the row end read
+// whatever index the row holds there (or zero past the row's buffer), and
+// the position load of any such index stays inside the positions' buffer
+// or returns zero; the body masks those slots as before.  Fewer vector
+// instructions for more gathered bytes: it pays for the forms whose pair
+// terms are longest (the two-element tight-binding form).
+template <int U, int WORDS, bool MASKED = true, typename Body>
 __device__ __forceinline__ void walk_buf(const __amdgpu_buffer_rsrc_t &xs_r, const __amdgpu_buffer_rsrc_t &row_r,
                                          int32_t cnt, int sub, Body &&body)
 {
@@ -107,7 +114,7 @@ __device__ __forceinline__ void walk_buf(const __amdgpu_buffer_rsrc_t &xs_r, con
         uint32_t j[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            ok[u] = t + u * kSlice < cnt;
+            ok[u] = !MASKED || t + u * kSlice < cnt;
             j[u] = __builtin_amdgcn_raw_buffer_load_b32(row_r, ok[u] ? off + u * 256u : kOut, 0, 0);
         }
         uint4 pj[U];

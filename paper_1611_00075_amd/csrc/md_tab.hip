@@ -216,14 +216,14 @@ __global__ __launch_bounds__(kTabBlock) void k_tab_force(int64_t n, const uint4 
                     disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
                     const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
                     const bool in = t0 + u * kSlice < cnt && r2 < p.cut2u;
-                    const float ru = __builtin_amdgcn_sqrtf(r2);
+                    const float ir = __builtin_amdgcn_rsqf(r2);   // 1/r and r = r2 / r
                     float q;
-                    const int k = tab_cell(ru * p.len * p.inv_dr, p.top_r, p.m, q);
+                    const int k = tab_cell(r2 * ir * p.len * p.inv_dr, p.top_r, p.m, q);
                     const float4 cp = lds_tab[k], cf = lds_tab[p.m + k];
                     const float fsum = fpi + __uint_as_float(pj[u].w);
                     // dU/dr = [(F'_i + F'_j) dpsi/ds + dPhi/ds] / dr; g = -(dU/dr) / r_u
                     const float dUds = __builtin_fmaf(fsum, tab_ds(cp, q), tab_ds(cf, q));
-                    float g = -dUds * p.inv_dr * __builtin_amdgcn_rcpf(ru);
+                    float g = -dUds * p.inv_dr * ir;
                     g = in ? g : 0.f;
                     bx = __builtin_fmaf(g, dx, bx);
                     by = __builtin_fmaf(g, dy, by);
