@@ -494,7 +494,8 @@ __global__ __launch_bounds__(kBlock) void k_mlp_force(int64_t n, MlpArgs p, cons
                 disp<false>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
                 const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
                 const bool in = t0 + u * kSlice < cnt && r2 < p.rc2;
-                const float r = __builtin_amdgcn_sqrtf(r2);
+                const float ir = __builtin_amdgcn_rsqf(r2);   // 1/r, and r = r2 / r
+                const float r = r2 * ir;
                 const float t = r - p.c8;
                 float e[kIn];
                 gaussians(p, t, e);
@@ -514,7 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_force(int64_t n, MlpArgs p, cons
                     S1 = __builtin_fmaf(float(k - 8), qk, S1);
                 }
                 const float sij = __builtin_fmaf(-fc * t, p.iw2, dfc) * S0 + fc * p.cw * S1;
-                const float gs = in ? -sij * __builtin_amdgcn_rcpf(r) : 0.f;
+                const float gs = in ? -sij * ir : 0.f;
                 acc_add<COMP>(fx, cx, gs, dx);
                 acc_add<COMP>(fy, cy, gs, dy);
                 acc_add<COMP>(fz, cz, gs, dz);
