@@ -160,12 +160,12 @@ int forces_tbm(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, 
                Gate = {});
 int set_elements(int64_t, const int32_t *, uint32_t *, hipStream_t);
 int workspace_upload(const md_grid_t *, int64_t, const int32_t *, void *, size_t, hipStream_t);
-struct Span;
-int span_forces_lj(const md_box_t *, int64_t, const Span &, const uint32_t *, int32_t, const int32_t *,
-                   const int32_t *, const md_lj_t *, float *, int32_t, double *, int64_t *, hipStream_t, Gate = {});
-int span_forces_eam(int, const md_box_t *, int64_t, const Span &, uint32_t *, int32_t, const int32_t *,
-                    const int32_t *, const md_fs_t *, float *, float *, float *, int32_t, double *, int64_t *,
-                    hipStream_t, Gate = {});
+struct BrickTab;
+int bricks_forces_lj(const md_box_t *, const BrickTab *, uint32_t, int64_t, const uint32_t *, int32_t, const int32_t *,
+                     const int32_t *, const md_lj_t *, float *, int32_t, double *, hipStream_t, Gate = {});
+int bricks_forces_eam(int, const md_box_t *, const BrickTab *, uint32_t, int64_t, uint32_t *, int32_t,
+                      const int32_t *, const int32_t *, const md_fs_t *, float *, float *, float *, int32_t, double *,
+                      hipStream_t, Gate = {});
 bool tab_ok(const md_tab_t *);
 int64_t tab_bytes(const md_tab_t *);
 int tab_pack(const md_tab_t *, const double *, const double *, const double *, const double *, const double *,

@@ -43,11 +43,23 @@ template <int TPA, int U, bool CUBIC, bool ENERGY, bool COMP>
 __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restrict__ xs,
                                                  int32_t cap, const int32_t *__restrict__ idx,
                                                  const int32_t *__restrict__ count, LJ32 p, float *__restrict__ f,
-                                                 double *__restrict__ part, Span sp)
+                                                 double *__restrict__ part, Span sp, const BrickTab *tab)
 {
     if (gated(p.gate)) return;
     static_assert(TPA == kSlice, "one slice per wave");
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t lblk = xcd_block(blockIdx.x, gridDim.x);   // partial rows by the launch's block
+    uint32_t blk = lblk;
+    if (tab) {
+        const BrickSel e = brick_select(tab, lblk);
+        blk = e.blk;
+        xs += e.slot0;
+        idx += e.slot0 * cap;
+        count += e.slot0;
+        f += e.atom0;
+        n = e.n_end;
+        sp.n_xs = e.n_xs;
+        sp.slice0 = e.slice0;
+    }
     const SliceLane sl = slice_lane(blk, sp.slice0);
     const int64_t i = sl.i;
     const int sub = sl.sub;
@@ -100,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restr
         double v[8] = {e, np, w[0] * u, w[1] * u, w[2] * u, w[3] * u, w[4] * u, w[5] * u};
         block_sum<8>(v, lds);
         if (threadIdx.x == 0)
-            for (int c = 0; c < 8; ++c) part[int64_t(blk) * 8 + c] = v[c];
+            for (int c = 0; c < 8; ++c) part[int64_t(lblk) * 8 + c] = v[c];
     }
 }
 
@@ -366,11 +378,24 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
                                                     int32_t cap, const int32_t *__restrict__ idx,
                                                     const int32_t *__restrict__ count, P p,
                                                     float *__restrict__ rho, float *__restrict__ fprime,
-                                                    double *__restrict__ part, Span sp)
+                                                    double *__restrict__ part, Span sp, const BrickTab *tab)
 {
     if (gated(p.gate)) return;
     static_assert(TPA == kSlice, "one slice per wave");
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t lblk = xcd_block(blockIdx.x, gridDim.x);
+    uint32_t blk = lblk;
+    if (tab) {
+        const BrickSel e = brick_select(tab, lblk);
+        blk = e.blk;
+        xs += e.slot0;
+        idx += e.slot0 * cap;
+        count += e.slot0;
+        rho += e.atom0;
+        fprime += e.atom0;
+        n = e.n_end;
+        sp.n_xs = e.n_xs;
+        sp.slice0 = e.slice0;
+    }
     const SliceLane sl = slice_lane(blk, sp.slice0);
     const int64_t i = sl.i;
     const int sub = sl.sub;
@@ -414,8 +439,8 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
         double v[1] = {Fi};
         block_sum<1>(v, lds);
         if (threadIdx.x == 0) {
-            part[int64_t(blk) * 8] = v[0];
-            for (int q = 1; q < 8; ++q) part[int64_t(blk) * 8 + q] = 0.0;
+            part[int64_t(lblk) * 8] = v[0];
+            for (int q = 1; q < 8; ++q) part[int64_t(lblk) * 8 + q] = 0.0;
         }
     }
 }
@@ -426,11 +451,26 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
                                                       int32_t cap, const int32_t *__restrict__ idx,
                                                       const int32_t *__restrict__ count, P p,
                                                       const float *__restrict__ rho, float *__restrict__ f,
-                                                      float *__restrict__ e_atom, double *__restrict__ part, Span sp)
+                                                      float *__restrict__ e_atom, double *__restrict__ part, Span sp,
+                                                      const BrickTab *tab)
 {
     if (gated(p.gate)) return;
     static_assert(TPA == kSlice, "one slice per wave");
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t lblk = xcd_block(blockIdx.x, gridDim.x);
+    uint32_t blk = lblk;
+    if (tab) {
+        const BrickSel e = brick_select(tab, lblk);
+        blk = e.blk;
+        xs += e.slot0;
+        idx += e.slot0 * cap;
+        count += e.slot0;
+        rho += e.atom0;
+        f += e.atom0;
+        if (e_atom) e_atom += e.atom0;
+        n = e.n_end;
+        sp.n_xs = e.n_xs;
+        sp.slice0 = e.slice0;
+    }
     const SliceLane sl = slice_lane(blk, sp.slice0);
     const int64_t i = sl.i;
     const int sub = sl.sub;
@@ -488,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
         double v[8] = {e, 0.0, w[0] * u, w[1] * u, w[2] * u, w[3] * u, w[4] * u, w[5] * u};
         block_sum<8>(v, lds);
         if (threadIdx.x == 0)
-            for (int c = 0; c < 8; ++c) part[int64_t(blk) * 8 + c] = v[c];
+            for (int c = 0; c < 8; ++c) part[int64_t(lblk) * 8 + c] = v[c];
     }
 }
 
@@ -509,20 +549,20 @@ struct List {
 
 template <int TPA, bool CUBIC, bool E, bool C>
 static void launch_lj32(uint32_t gb, hipStream_t s, int64_t n, const uint4 *q, const List &l, const LJ32 &p,
-                        float *f, double *part, const Span &sp)
+                        float *f, double *part, const Span &sp, const BrickTab *tab)
 {
     hipLaunchKernelGGL((k_lj32<TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx, l.cnt,
-                       p, f, part, sp);
+                       p, f, part, sp, tab);
 }
 
 template <int TPA, bool CUBIC>
 static void dispatch_lj32(bool e, bool c, uint32_t gb, hipStream_t s, int64_t n, const uint4 *q, const List &l,
-                          const LJ32 &p, float *f, double *part, const Span &sp)
+                          const LJ32 &p, float *f, double *part, const Span &sp, const BrickTab *tab = nullptr)
 {
-    if (e && c) launch_lj32<TPA, CUBIC, true, true>(gb, s, n, q, l, p, f, part, sp);
-    else if (e) launch_lj32<TPA, CUBIC, true, false>(gb, s, n, q, l, p, f, part, sp);
-    else if (c) launch_lj32<TPA, CUBIC, false, true>(gb, s, n, q, l, p, f, part, sp);
-    else launch_lj32<TPA, CUBIC, false, false>(gb, s, n, q, l, p, f, part, sp);
+    if (e && c) launch_lj32<TPA, CUBIC, true, true>(gb, s, n, q, l, p, f, part, sp, tab);
+    else if (e) launch_lj32<TPA, CUBIC, true, false>(gb, s, n, q, l, p, f, part, sp, tab);
+    else if (c) launch_lj32<TPA, CUBIC, false, true>(gb, s, n, q, l, p, f, part, sp, tab);
+    else launch_lj32<TPA, CUBIC, false, false>(gb, s, n, q, l, p, f, part, sp, tab);
 }
 
 // blocks of a launch over the slices from sp.slice0 to the one holding atom n-1
@@ -603,25 +643,26 @@ int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *x
 
 template <class P, int TPA, bool CUBIC, bool E, bool C>
 static void launch_eam(int passes, uint32_t gb, hipStream_t s, int64_t n, uint4 *q, const List &l, const P &p,
-                       float *rho, float *fprime, float *f, float *ea, double *part1, double *part2, const Span &sp)
+                       float *rho, float *fprime, float *f, float *ea, double *part1, double *part2, const Span &sp,
+                       const BrickTab *tab)
 {
     if (passes & 1)
         hipLaunchKernelGGL((k_eam_rho<P, TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap,
-                           l.idx, l.cnt, p, rho, fprime, part1, sp);
+                           l.idx, l.cnt, p, rho, fprime, part1, sp, tab);
     if (passes & 2)
         hipLaunchKernelGGL((k_eam_force<P, TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap,
-                           l.idx, l.cnt, p, rho, f, ea, part2, sp);
+                           l.idx, l.cnt, p, rho, f, ea, part2, sp, tab);
 }
 
 template <class P, int TPA, bool CUBIC>
 static void dispatch_eam(int passes, bool e, bool c, uint32_t gb, hipStream_t s, int64_t n, uint4 *q,
                          const List &l, const P &p, float *rho, float *fprime, float *f, float *ea, double *p1,
-                         double *p2, const Span &sp)
+                         double *p2, const Span &sp, const BrickTab *tab = nullptr)
 {
-    if (e && c) launch_eam<P, TPA, CUBIC, true, true>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp);
-    else if (e) launch_eam<P, TPA, CUBIC, true, false>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp);
-    else if (c) launch_eam<P, TPA, CUBIC, false, true>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp);
-    else launch_eam<P, TPA, CUBIC, false, false>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp);
+    if (e && c) launch_eam<P, TPA, CUBIC, true, true>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp, tab);
+    else if (e) launch_eam<P, TPA, CUBIC, true, false>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp, tab);
+    else if (c) launch_eam<P, TPA, CUBIC, false, true>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp, tab);
+    else launch_eam<P, TPA, CUBIC, false, false>(passes, gb, s, n, q, l, p, rho, fprime, f, ea, p1, p2, sp, tab);
 }
 
 // Both passes of an embedded-atom form P (geometry fields set here).
@@ -749,45 +790,45 @@ int forces_tbm(const md_box_t *box, int64_t n, uint32_t *xs, int32_t cap, const 
                            w, s);
 }
 
-// ---- one range of one brick of a domain decomposition ----
-// Atoms [8 sp.slice0, n) of a brick whose frame box is `vbox`; sp.n_xs
-// atoms (local and ghost) may be gathered.  Partial energy rows (when
-// MD_ENERGY is set) are written from `part` on; *rows gets their number.
+// ---- ranges of the bricks of a domain decomposition, one launch ----
+// `tab` (device) gives each brick's atom range and bases (BrickTab); gb
+// logical blocks in all; xs, idx, count, f, rho, fprime are the arrays of
+// all bricks (slot and atom 0); fs the stride of f's components.  Partial
+// energy rows (MD_ENERGY) go to part[0 .. gb).
 
-int span_forces_lj(const md_box_t *vbox, int64_t n, const Span &sp, const uint32_t *xs, int32_t cap,
-                   const int32_t *idx, const int32_t *cnt, const md_lj_t *lj, float *f, int32_t flags, double *part,
-                   int64_t *rows, hipStream_t s, Gate gate)
+int bricks_forces_lj(const md_box_t *vbox, const BrickTab *tab, uint32_t gb, int64_t fs, const uint32_t *xs,
+                     int32_t cap, const int32_t *idx, const int32_t *cnt, const md_lj_t *lj, float *f, int32_t flags,
+                     double *part, hipStream_t s, Gate gate)
 {
-    const uint32_t gb = blocks_span(n, sp);
-    *rows = gb;
     if (gb == 0) return MD_OK;
     const LJ32 p = lj_constants(vbox, lj, gate);
     const List l{cap, idx, cnt};
     const uint4 *q = reinterpret_cast<const uint4 *>(xs);
     const bool energy = flags & MD_ENERGY, comp = !(flags & MD_NO_COMPENSATE);
-    if (is_cubic(vbox)) dispatch_lj32<kTPA, true>(energy, comp, gb, s, n, q, l, p, f, part, sp);
-    else dispatch_lj32<kTPA, false>(energy, comp, gb, s, n, q, l, p, f, part, sp);
+    const Span sp{0, fs, 0u};
+    if (is_cubic(vbox)) dispatch_lj32<kTPA, true>(energy, comp, gb, s, 0, q, l, p, f, part, sp, tab);
+    else dispatch_lj32<kTPA, false>(energy, comp, gb, s, 0, q, l, p, f, part, sp, tab);
     MD_HIP_TRY(hipGetLastError());
     return MD_OK;
 }
 
 // pass: 1 = densities and F' (rho, fprime, the fourth words), 2 = forces
-int span_forces_eam(int pass, const md_box_t *vbox, int64_t n, const Span &sp, uint32_t *xs, int32_t cap,
-                    const int32_t *idx, const int32_t *cnt, const md_fs_t *fs, float *rho, float *fprime, float *f,
-                    int32_t flags, double *part, int64_t *rows, hipStream_t s, Gate gate)
+int bricks_forces_eam(int pass, const md_box_t *vbox, const BrickTab *tab, uint32_t gb, int64_t fs, uint32_t *xs,
+                      int32_t cap, const int32_t *idx, const int32_t *cnt, const md_fs_t *fsp, float *rho,
+                      float *fprime, float *f, int32_t flags, double *part, hipStream_t s, Gate gate)
 {
-    const uint32_t gb = blocks_span(n, sp);
-    *rows = gb;
     if (gb == 0) return MD_OK;
-    const FS32 p = fs_constants(vbox, fs, gate);
+    const FS32 p = fs_constants(vbox, fsp, gate);
     const List l{cap, idx, cnt};
     uint4 *q = reinterpret_cast<uint4 *>(xs);
     const bool energy = flags & MD_ENERGY, comp = !(flags & MD_NO_COMPENSATE);
+    const Span sp{0, fs, 0u};
     if (is_cubic(vbox))
-        dispatch_eam<FS32, kTPA, true>(pass, energy, comp, gb, s, n, q, l, p, rho, fprime, f, nullptr, part, part, sp);
+        dispatch_eam<FS32, kTPA, true>(pass, energy, comp, gb, s, 0, q, l, p, rho, fprime, f, nullptr, part, part, sp,
+                                       tab);
     else
-        dispatch_eam<FS32, kTPA, false>(pass, energy, comp, gb, s, n, q, l, p, rho, fprime, f, nullptr, part, part,
-                                        sp);
+        dispatch_eam<FS32, kTPA, false>(pass, energy, comp, gb, s, 0, q, l, p, rho, fprime, f, nullptr, part, part,
+                                        sp, tab);
     MD_HIP_TRY(hipGetLastError());
     return MD_OK;
 }

@@ -375,7 +375,7 @@ DdGeom geom(const md_dd_t *dd)
 // scratch layout in dws
 struct DdScratch {
     size_t off, bstart, slot0, key, perm, mask, cnt, eoff, ent_atom, ent_key, order, hist, offs, starts, bsum,
-        xt, xb, xsorted, cell, permt, cstart, gperm, inv, part1, part2, word, total;
+        xt, xb, xsorted, cell, permt, cstart, gperm, inv, part1, part2, word, tab_in, tab_out, total;
     int64_t rows, hist_len;
 };
 
@@ -420,8 +420,35 @@ DdScratch scratch_layout(const md_dd_t *dd)
     l.part1 = take(size_t(l.rows) * 8 * 8);
     l.part2 = take(size_t(l.rows) * 8 * 8);
     l.word = take(64);
+    l.tab_in = take(sizeof(BrickTab));
+    l.tab_out = take(sizeof(BrickTab));
     l.total = o;
     return l;
+}
+
+// The inner (or outer) atoms of every brick as one launch: per brick the
+// slices of its inner atoms (whole slices only) or the rest of its atoms.
+// Returns the launch's logical blocks.
+uint32_t fill_tab(const md_dd_t *dd, bool inner, BrickTab &t)
+{
+    t = BrickTab{};
+    t.nb = dd->n_bricks;
+    int64_t blk = 0;
+    for (int e = 0; e < dd->n_bricks; ++e) {
+        const int64_t nt = dd->brick_start[e + 1] - dd->brick_start[e];
+        const int64_t gt = dd->ghost_start[e + 1] - dd->ghost_start[e];
+        const uint32_t split = uint32_t(dd->n_inner[e] / kSlice);
+        t.blk0[e] = blk;
+        t.slot0[e] = dd->slot0[e];
+        t.atom0[e] = dd->brick_start[e];
+        t.n_xs[e] = nt + gt;
+        t.slice0[e] = inner ? 0u : split;
+        t.n_end[e] = inner ? int64_t(split) * kSlice : nt;
+        const int64_t slices = (t.n_end[e] + kSlice - 1) / kSlice - int64_t(t.slice0[e]);
+        blk += slices > 0 ? (slices + kBlock / kWave - 1) / (kBlock / kWave) : 0;
+    }
+    t.blk0[dd->n_bricks] = blk;
+    return uint32_t(blk);
 }
 
 // stable partition of m keys in [0, K): perm and start[K + 1] (device)
@@ -687,6 +714,11 @@ int md_dd_rebuild(md_dd_t *dd, void *stream)
                            dd->gh_src_slot, ws_ptr<int64_t>(ws, l.bstart), ws_ptr<int64_t>(ws, l.slot0), P);
     }
     MD_HIP_TRY(hipGetLastError());
+    BrickTab tin, tout;
+    fill_tab(dd, true, tin);
+    fill_tab(dd, false, tout);
+    MD_HIP_TRY(hipMemcpyAsync(ws_ptr<char>(ws, l.tab_in), &tin, sizeof(BrickTab), hipMemcpyHostToDevice, s));
+    MD_HIP_TRY(hipMemcpyAsync(ws_ptr<char>(ws, l.tab_out), &tout, sizeof(BrickTab), hipMemcpyHostToDevice, s));
     MD_HIP_TRY(hipStreamSynchronize(s));
     ++dd->builds;
     return MD_OK;
@@ -743,38 +775,25 @@ int dd_forces(md_dd_t *dd, double *ev, int32_t flags, void *stream, void *comm, 
 
     double *part1 = ws_ptr<double>(ws, l.part1), *part2 = ws_ptr<double>(ws, l.part2);
     int64_t rows1 = 0, rows2 = 0;
-    auto span_of = [&](int t, bool inner) {
-        const int64_t nt = dd->brick_start[t + 1] - dd->brick_start[t];
-        const int64_t gt = dd->ghost_start[t + 1] - dd->ghost_start[t];
-        const uint32_t split = uint32_t(dd->n_inner[t] / kSlice);
-        Span sp{nt + gt, n, inner ? 0u : split};
-        const int64_t end = inner ? int64_t(split) * kSlice : nt;
-        return std::make_pair(sp, end);
-    };
-    // one phase (inner or outer) of one pass over all bricks
+    BrickTab host_tab;
+    const uint32_t gb_in = fill_tab(dd, true, host_tab), gb_out = fill_tab(dd, false, host_tab);
+    if (int64_t(gb_in) + gb_out > l.rows) return MD_ERR_WORKSPACE;
+    const BrickTab *tab_in = ws_ptr<BrickTab>(ws, l.tab_in), *tab_out = ws_ptr<BrickTab>(ws, l.tab_out);
+    // one phase (inner or outer atoms of every brick) of one pass, one launch
     auto phase = [&](int pass, bool inner) -> int {
-        for (int t = 0; t < P; ++t) {
-            const auto se = span_of(t, inner);
-            const Span &sp = se.first;
-            const int64_t end = se.second;
-            if (end <= int64_t(sp.slice0) * kSlice) continue;
-            const int64_t b0 = dd->brick_start[t], s0 = dd->slot0[t];
-            const int32_t *idx = dd->idx + s0 * dd->row_cap, *cnt = dd->count + s0;
-            int64_t rows = 0;
-            double *part = (pass == 2 ? part2 + rows2 * 8 : part1 + rows1 * 8);
-            const int64_t launch_rows = ((end + kSlice - 1) / kSlice - sp.slice0 + kBlock / kWave - 1) / (kBlock / kWave);
-            if ((pass == 2 ? rows2 : rows1) + launch_rows > l.rows) return MD_ERR_WORKSPACE;
-            int rc;
-            if (dd->potential == MD_POT_LJ)
-                rc = span_forces_lj(&dd->vbox, end, sp, dd->xs + 4 * s0, dd->row_cap, idx, cnt, &dd->lj, dd->f + b0, fl,
-                                    part, &rows, s);
-            else
-                rc = span_forces_eam(pass, &dd->vbox, end, sp, dd->xs + 4 * s0, dd->row_cap, idx, cnt, &dd->fs,
-                                     dd->rho + b0, dd->fprime + b0, dd->f + b0, fl, part, &rows, s);
-            if (rc) return rc;
-            (pass == 2 ? rows2 : rows1) += rows;
-        }
-        return MD_OK;
+        const BrickTab *tab = inner ? tab_in : tab_out;
+        const uint32_t gb = inner ? gb_in : gb_out;
+        int64_t &rows = pass == 2 ? rows2 : rows1;
+        double *part = (pass == 2 ? part2 : part1) + rows * 8;
+        int rc;
+        if (dd->potential == MD_POT_LJ)
+            rc = bricks_forces_lj(&dd->vbox, tab, gb, n, dd->xs, dd->row_cap, dd->idx, dd->count, &dd->lj, dd->f, fl,
+                                  part, s);
+        else
+            rc = bricks_forces_eam(pass, &dd->vbox, tab, gb, n, dd->xs, dd->row_cap, dd->idx, dd->count, &dd->fs,
+                                   dd->rho, dd->fprime, dd->f, fl, part, s);
+        rows += gb;
+        return rc;
     };
     if (dd->potential == MD_POT_LJ) {
         if (int rc = phase(1, true)) return rc;

@@ -146,6 +146,36 @@ struct Span {
 
 __host__ __device__ inline Span whole(int64_t n) { return Span{n, n, 0u}; }
 
+// Several bricks of a domain decomposition in one launch.  Logical block b
+// belongs to brick e with blk0[e] <= b < blk0[e + 1]; for its blocks the
+// kernel's position, list and count arrays start at the brick's first slot
+// (slot0[e]) and its per-atom outputs at the brick's first atom (atom0[e]);
+// its span is (n_xs[e], the launch's force stride, slice0[e]) over atoms
+// below n_end[e] of the brick.
+struct BrickTab {
+    int32_t nb;
+    int64_t blk0[MD_DD_MAX_BRICKS + 1];
+    int64_t slot0[MD_DD_MAX_BRICKS], atom0[MD_DD_MAX_BRICKS], n_end[MD_DD_MAX_BRICKS], n_xs[MD_DD_MAX_BRICKS];
+    uint32_t slice0[MD_DD_MAX_BRICKS];
+};
+
+struct BrickSel {
+    uint32_t blk;                    // block within the brick's range
+    int64_t slot0, atom0, n_end, n_xs;
+    uint32_t slice0;
+};
+
+__device__ __forceinline__ BrickSel brick_select(const BrickTab *t, uint32_t b)
+{
+    int lo = 0, hi = t->nb;   // blk0[lo] <= b < blk0[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (t->blk0[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return {uint32_t(b - t->blk0[lo]), t->slot0[lo], t->atom0[lo], t->n_end[lo], t->n_xs[lo], t->slice0[lo]};
+}
+
 // Buffers of a force kernel's wavefront: the positions (n_xs < 2^28 atoms)
 // and its slice's block of the list.
 struct SliceBufs {
