@@ -326,7 +326,7 @@ def main():
             "bound": "hbm", "kernel": "k_lj32 (md_forces_lj)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("k_lj32_lj_voids_1.23M"),
-            "valu_busy_pct": recorded("k_lj32_lj_voids_1.23M", "valu_busy_pct"),
+            "valu_inst_per_cu_clk": recorded("k_lj32_lj_voids_1.23M", "valu_inst_per_cu_clk"),
             "bytes_per_launch": byt, "launch_ms": f_ms,
         },
         "phases_ms_per_call_api": {k: v[0] for k, v in r["phases"].items()},
@@ -359,8 +359,8 @@ def main():
                 "forces_frac_hbm": b3 / (f3 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "forces_frac_copy": b3 / (f3 * 1e-3) / 1e9 / copy_gbs,
                 "forces_traffic_bytes": recorded_pair("k_eam_rho_cu_4M", "k_eam_force_cu_4M"),
-                "valu_busy_pct": [recorded("k_eam_rho_cu_4M", "valu_busy_pct"),
-                                  recorded("k_eam_force_cu_4M", "valu_busy_pct")],
+                "valu_inst_per_cu_clk": [recorded("k_eam_rho_cu_4M", "valu_inst_per_cu_clk"),
+                                         recorded("k_eam_force_cu_4M", "valu_inst_per_cu_clk")],
                 "forces_bytes": b3,
                 "phases_ms_per_call_api": {k: v[0] for k, v in r3["phases"].items()},
             }
@@ -517,7 +517,7 @@ def main():
             "achieved": fl / (t_ms * 1e-3) / 1e12, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": fl / (t_ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS,
             "traffic": recorded_traffic("k_mlp_force_cu_4M"),
-            "valu_busy_pct": recorded("k_mlp_force_cu_4M", "valu_busy_pct"),
+            "valu_inst_per_cu_clk": recorded("k_mlp_force_cu_4M", "valu_inst_per_cu_clk"),
             "net_mfma_util_pct": recorded("k_mlp_net_cu_4M", "mfma_util_pct"),
             "launch_ms": t_ms,
         }
