@@ -27,6 +27,7 @@
 
 #include "md_pair.h"
 
+
 namespace md {
 
 // ---------------------------------------------------------------------------
@@ -70,15 +71,16 @@ __global__ __launch_bounds__(kBlock) void k_lj32(int64_t n, const uint4 *__restr
     if (i < n) {
         const uint4 pi = xs[i];
         const int32_t cnt = min(count[i], cap);
-        walk_buf<U, 3>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t) {
-            // the U pair forces are summed plainly, the sum is added compensated
+        // a batch's pair forces are summed plainly, the sum added compensated
+        walk_split<U, 3>(b.xs, b.row, cnt, sub, [&](const auto &pj, int32_t t, auto masked) {
+            constexpr int K = sizeof(pj) / sizeof(uint4);
             float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < K; ++u) {
                 float dx, dy, dz;
                 disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
                 const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                const bool in = t + u * TPA < cnt && r2 < p.rc2;
+                const bool in = (!decltype(masked)::value || t + u * TPA < cnt) && r2 < p.rc2;
                 const float ir2 = __builtin_amdgcn_rcpf(r2);
                 const float s2 = p.sig2 * ir2;
                 const float s6 = s2 * s2 * s2;
@@ -208,7 +210,7 @@ struct FS32 {
     float d, c, p0, p1, p2, A;  // physical
     Gate gate;
     static constexpr int kRhoWords = 3;   // words of a neighbour's scaled coordinates pass 1 reads
-    static constexpr bool kMasked = true; // row walk with per-slot selects
+    static constexpr bool kSplit = true;  // row walk: full batches, then one masked tail batch
 };
 
 // Second-moment tight-binding form: psi = exp2(cq - kq r) S(r),
@@ -224,7 +226,7 @@ struct TB32 {
     float A;                // embedding prefactor (1)
     Gate gate;
     static constexpr int kRhoWords = 3;
-    static constexpr bool kMasked = true;
+    static constexpr bool kSplit = true;
 };
 
 // Two elements: the tight-binding constants per pair kind k = t_i + t_j
@@ -244,7 +246,9 @@ struct TBM32 {
     float A;                // embedding prefactor (1)
     Gate gate;
     static constexpr int kRhoWords = 4;
-    static constexpr bool kMasked = false;   // the longer pair terms favour fewer selects
+    // whole batches without selects, slots past the row end masked in the
+    // pair term: the longer pair terms favour fewer selects over fewer slots
+    static constexpr bool kSplit = false;
 };
 
 // ---- pair terms of the forms ------------------------------------------------
@@ -407,14 +411,15 @@ __global__ __launch_bounds__(kBlock) void k_eam_rho(int64_t n, uint4 *__restrict
         const uint4 pi = xs[i];
         wi = pi.w;
         const int32_t cnt = min(count[i], cap);
-        walk_buf<U, P::kRhoWords, P::kMasked>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
+        walk_form<P::kSplit, U, P::kRhoWords>(b.xs, b.row, cnt, sub, [&](const auto &pj, int32_t t0, auto masked) {
+            constexpr int K = sizeof(pj) / sizeof(uint4);
             float bs = 0.f;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < K; ++u) {
                 float dx, dy, dz;
                 disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
                 const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                bs += rho_term(p, r2, t0 + u * TPA < cnt, pi.w, pj[u].w);
+                bs += rho_term(p, r2, !decltype(masked)::value || t0 + u * TPA < cnt, pi.w, pj[u].w);
             }
             acc_sum<COMP>(s, c, bs);
         });
@@ -481,15 +486,16 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
     if (i < n) {
         const uint4 pi = xs[i];
         const int32_t cnt = min(count[i], cap);
-        walk_buf<U, 4, P::kMasked>(b.xs, b.row, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
+        walk_form<P::kSplit, U, 4>(b.xs, b.row, cnt, sub, [&](const auto &pj, int32_t t0, auto masked) {
+            constexpr int K = sizeof(pj) / sizeof(uint4);
             float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < K; ++u) {
                 float dx, dy, dz;
                 disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
                 const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
                 // -(dU/dr) / r in the displacement unit: F = g * (dx, dy, dz)
-                const PairOut o = force_term(p, r2, t0 + u * TPA < cnt, pi.w, pj[u].w);
+                const PairOut o = force_term(p, r2, !decltype(masked)::value || t0 + u * TPA < cnt, pi.w, pj[u].w);
                 const float g = o.g;
                 bx = __builtin_fmaf(g, dx, bx);
                 by = __builtin_fmaf(g, dy, by);
@@ -536,7 +542,8 @@ __global__ __launch_bounds__(kBlock) void k_eam_force(int64_t n, const uint4 *__
 // launchers
 // ---------------------------------------------------------------------------
 constexpr int kTPA = kSlice;   // lanes per atom of the FP32 kernels
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 4;     // row entries per lane per batch (embedded-atom passes)
+constexpr int kUnrollLJ = 6;   // LJ: rows of ~70 entries take two batches (measured best of 2-12)
 
 static uint32_t blocks_for(int64_t n, int tpa) { return uint32_t((n * tpa + kBlock - 1) / kBlock); }
 
@@ -551,7 +558,7 @@ template <int TPA, bool CUBIC, bool E, bool C>
 static void launch_lj32(uint32_t gb, hipStream_t s, int64_t n, const uint4 *q, const List &l, const LJ32 &p,
                         float *f, double *part, const Span &sp, const BrickTab *tab)
 {
-    hipLaunchKernelGGL((k_lj32<TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx, l.cnt,
+    hipLaunchKernelGGL((k_lj32<TPA, kUnrollLJ, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap, l.idx, l.cnt,
                        p, f, part, sp, tab);
 }
 

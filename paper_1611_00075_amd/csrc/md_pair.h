@@ -45,26 +45,6 @@ __device__ __forceinline__ const int32_t *ell_row(const int32_t *idx, int64_t i,
 
 __device__ __forceinline__ int64_t ell_pos(int32_t e) { return int64_t(e / kSlice) * (kSlice * kSlice) + e % kSlice; }
 
-// Walk row entries [0, cnt) with stride U*TPA starting at `sub`;
-// body(pj, valid).  With lane = 8 * atom + sub the lanes of a wave read one
-// contiguous 256-byte run of the list per load, and each quarter-wave
-// gathers 8 consecutive neighbours of one atom.
-template <int TPA, int U, typename Body>
-__device__ __forceinline__ void walk_row(const uint4 *__restrict__ xs, const int32_t *__restrict__ row, int32_t cnt,
-                                         int sub, Body &&body)
-{
-    for (int32_t t = sub; t < cnt; t += U * TPA) {
-        int32_t j[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) j[u] = row[ell_pos(min(t + u * TPA, cnt - 1))];
-        uint4 pj[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) pj[u] = xs[j[u]];
-#pragma unroll
-        for (int u = 0; u < U; ++u) body(pj[u], t + u * TPA < cnt);
-    }
-}
-
 // s += v with the running error of the sum compensated (Kahan).
 template <bool COMP>
 __device__ __forceinline__ void acc_sum(float &s, float &c, float v)
@@ -87,15 +67,23 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, int(bytes), 0x00020000);
 }
 
+// Compile-time flag handed to a row walk's body: whether slots of the
+// batch may lie past the row's end (the body must then mask them).
+template <bool M>
+struct Masked {
+    static constexpr bool value = M;
+};
+
 // Row walk through buffer loads.  The wavefront holds one slice of 8 atoms
 // (lane = 8 * atom + sub); the slice's block of the list is one buffer
 // (row_r, cap * 32 bytes), in which entry sub + 8 q of the lane's atom sits
 // at byte q * 256 + 4 * lane: one lane offset plus an immediate per load.
 // Per iteration each lane reads U entries, then their U positions (xs_r,
 // 16 bytes per atom, WORDS = 3 or 4 words read), then calls
-// body(pj, t) with the U positions of entries t + 8 u.  For entries past
-// the row end both loads are given an offset outside their buffer, so they
-// move no data and return zero; the body masks them (t + 8 u >= cnt).
+// body(pj, t, Masked<true>) with the U positions of entries t + 8 u.  For
+// entries past the row end both loads are given an offset outside their
+// buffer, so they move no data and return zero; the body masks them
+// (t + 8 u >= cnt).
 //
 // MASKED = false drops the two per-slot selects: slots past the row end read
 // whatever index the row holds there (or zero past the row's buffer), and
@@ -129,8 +117,68 @@ __device__ __forceinline__ void walk_buf(const __amdgpu_buffer_rsrc_t &xs_r, con
                 pj[u] = make_uint4(v[0], v[1], v[2], 0u);
             }
         }
-        body(pj, t);
+        body(pj, t, Masked<true>{});
     }
+}
+
+// Row walk in two parts.  Full batches: while all U entries t + 8 u of the
+// lane are inside the row, U indices then U positions are loaded with no
+// per-slot selects and body(pj, t, Masked<false>) gets U positions, all of
+// them real neighbours.  Tail (1 to U - 1 entries left): one batch of
+// U - 1 slots, body(pj, t, Masked<true>) with pj of length U - 1, slots
+// past the end given the out-of-range offset as in walk_buf.  A lane thus
+// evaluates fewer slots than U * ceil(cnt / 8U) and makes no selects in
+// its full batches.
+template <int U, int WORDS, typename Body>
+__device__ __forceinline__ void walk_split(const __amdgpu_buffer_rsrc_t &xs_r, const __amdgpu_buffer_rsrc_t &row_r,
+                                           int32_t cnt, int sub, Body &&body)
+{
+    static_assert(U > 1, "a tail batch holds U - 1 slots");
+    constexpr uint32_t kOut = 0xfffffff0u;
+    auto pos = [&](uint32_t o) {
+        if (WORDS == 4) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(xs_r, o, 0, 0);
+            return make_uint4(v[0], v[1], v[2], v[3]);
+        } else {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b96(xs_r, o, 0, 0);
+            return make_uint4(v[0], v[1], v[2], 0u);
+        }
+    };
+    uint32_t off = (threadIdx.x % kWave) * 4u;
+    int32_t t = sub;
+    for (; t + (U - 1) * kSlice < cnt; t += U * kSlice, off += U * 256u) {
+        uint32_t j[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = __builtin_amdgcn_raw_buffer_load_b32(row_r, off + u * 256u, 0, 0);
+        uint4 pj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pj[u] = pos(j[u] << 4);
+        body(pj, t, Masked<false>{});
+    }
+    if (t < cnt) {
+        constexpr int V = U - 1;
+        bool ok[V];
+        uint32_t j[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            ok[u] = t + u * kSlice < cnt;
+            j[u] = __builtin_amdgcn_raw_buffer_load_b32(row_r, ok[u] ? off + u * 256u : kOut, 0, 0);
+        }
+        uint4 pj[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) pj[u] = pos(ok[u] ? j[u] << 4 : kOut);
+        body(pj, t, Masked<true>{});
+    }
+}
+
+// The row walk of a pair form: split (SPLIT) or whole batches with no
+// selects (walk_buf without masking).
+template <bool SPLIT, int U, int WORDS, typename Body>
+__device__ __forceinline__ void walk_form(const __amdgpu_buffer_rsrc_t &xs_r, const __amdgpu_buffer_rsrc_t &row_r,
+                                          int32_t cnt, int sub, Body &&body)
+{
+    if constexpr (SPLIT) walk_split<U, WORDS>(xs_r, row_r, cnt, sub, body);
+    else walk_buf<U, WORDS, false>(xs_r, row_r, cnt, sub, body);
 }
 
 // The atoms a force launch covers: the slices from slice0 on, rows and

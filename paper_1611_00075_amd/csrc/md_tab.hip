@@ -143,17 +143,18 @@ __global__ __launch_bounds__(kTabBlock) void k_tab_rho(int64_t n, uint4 *__restr
         if (i < n) {
             const uint4 pi = xs[i];
             const int32_t cnt = min(count[i], cap);
-            walk_buf<U, 3>(xs_r, row_r, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
+            walk_split<U, 3>(xs_r, row_r, cnt, sub, [&](const auto &pj, int32_t t0, auto masked) {
+                constexpr int K = sizeof(pj) / sizeof(uint4);
                 float bs = 0.f;
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
+                for (int u = 0; u < K; ++u) {
                     float dx, dy, dz;
                     disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
                     const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
                     float q;
                     const int k = tab_cell(__builtin_amdgcn_sqrtf(r2) * p.len * p.inv_dr, p.top_r, p.m, q);
                     const float psi = tab_val(lds_tab[k], q);
-                    bs += (t0 + u * kSlice < cnt && r2 < p.cut2u) ? psi : 0.f;
+                    bs += ((!decltype(masked)::value || t0 + u * kSlice < cnt) && r2 < p.cut2u) ? psi : 0.f;
                 }
                 acc_sum<COMP>(s, c, bs);
             });
@@ -208,14 +209,15 @@ __global__ __launch_bounds__(kTabBlock) void k_tab_force(int64_t n, const uint4 
             const uint4 pi = xs[i];
             const float fpi = __uint_as_float(pi.w);
             const int32_t cnt = min(count[i], cap);
-            walk_buf<U, 4>(xs_r, row_r, cnt, sub, [&](const uint4 (&pj)[U], int32_t t0) {
+            walk_split<U, 4>(xs_r, row_r, cnt, sub, [&](const auto &pj, int32_t t0, auto masked) {
+                constexpr int K = sizeof(pj) / sizeof(uint4);
                 float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
+                for (int u = 0; u < K; ++u) {
                     float dx, dy, dz;
                     disp<CUBIC>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
                     const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                    const bool in = t0 + u * kSlice < cnt && r2 < p.cut2u;
+                    const bool in = (!decltype(masked)::value || t0 + u * kSlice < cnt) && r2 < p.cut2u;
                     const float ir = __builtin_amdgcn_rsqf(r2);   // 1/r and r = r2 / r
                     float q;
                     const int k = tab_cell(r2 * ir * p.len * p.inv_dr, p.top_r, p.m, q);
