@@ -540,7 +540,8 @@ int md_dd_forces(md_dd_t *dd, double *ev, int32_t flags, void *stream,
 int md_dd_run(md_dd_t *dd, int64_t steps, double dt, double accel,
               double skin, void *stream, void *comm);
 
-/* Destroys the events md_dd_forces created. */
+/* Destroys the events md_dd_forces created; MD_ERR_HIP if the runtime
+ * reports a failure (every event handle is cleared either way). */
 int md_dd_release(md_dd_t *dd);
 
 /* ---- step a7: velocity Verlet ---- */

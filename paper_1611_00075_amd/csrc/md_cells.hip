@@ -187,6 +187,57 @@ int scale_positions(const md_box_t *box, int64_t n, const double *x, uint32_t *x
     return MD_OK;
 }
 
+// Positions, velocities and input indices into the sorted order in two
+// passes: gather from the old order into xr (the new reference positions),
+// vt and it; then copy vt, it and xr back into the state arrays and, with
+// xs, write the scaled coordinates of the new positions.
+__global__ __launch_bounds__(kBlock) void k_reorder_gather(int64_t n, const int32_t *__restrict__ perm,
+                                                           const double *__restrict__ x,
+                                                           const double *__restrict__ v,
+                                                           const int32_t *__restrict__ ids, double *__restrict__ xr,
+                                                           double *__restrict__ vt, int32_t *__restrict__ it)
+{
+    const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int64_t j = perm[k];
+    for (int c = 0; c < 3; ++c) {
+        xr[c * n + k] = x[c * n + j];
+        vt[c * n + k] = v[c * n + j];
+    }
+    it[k] = ids[j];
+}
+
+__global__ __launch_bounds__(kBlock) void k_reorder_put(int64_t n, const double *__restrict__ xr,
+                                                        const double *__restrict__ vt,
+                                                        const int32_t *__restrict__ it, double *__restrict__ x,
+                                                        double *__restrict__ v, int32_t *__restrict__ ids, double k0,
+                                                        double k1, double k2, uint4 *__restrict__ xs)
+{
+    const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (k >= n) return;
+    double p[3];
+    for (int c = 0; c < 3; ++c) {
+        p[c] = xr[c * n + k];
+        x[c * n + k] = p[c];
+        v[c * n + k] = vt[c * n + k];
+    }
+    ids[k] = it[k];
+    if (xs) xs[k] = make_uint4(scale1(p[0], k0), scale1(p[1], k1), scale1(p[2], k2), 0u);
+}
+
+int reorder_state(int64_t n, const int32_t *perm, double *x, double *v, int32_t *ids, double *xref, double *vtmp,
+                  int32_t *itmp, const md_box_t *box, uint32_t *xs, hipStream_t s)
+{
+    if (n <= 0) return MD_OK;
+    const double two32 = 4294967296.0;
+    const uint32_t gb = uint32_t((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_reorder_gather, dim3(gb), dim3(kBlock), 0, s, n, perm, x, v, ids, xref, vtmp, itmp);
+    hipLaunchKernelGGL(k_reorder_put, dim3(gb), dim3(kBlock), 0, s, n, xref, vtmp, itmp, x, v, ids,
+                       two32 / box->L[0], two32 / box->L[1], two32 / box->L[2], reinterpret_cast<uint4 *>(xs));
+    MD_HIP_TRY(hipGetLastError());
+    return MD_OK;
+}
+
 // The element of each atom (0 or 1; only bit 0 is used) into the fourth word
 // of its scaled coordinates.
 __global__ __launch_bounds__(kBlock) void k_set_elements(int64_t n, const int32_t *types, uint4 *xs)

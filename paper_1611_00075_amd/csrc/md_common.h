@@ -145,6 +145,8 @@ int bin_cells(const md_grid_t *, int64_t, double *, int32_t *, int32_t *, int32_
               hipStream_t);
 int permute(int64_t, int32_t, const int32_t *, const void *, void *, int32_t, hipStream_t);
 int scale_positions(const md_box_t *, int64_t, const double *, uint32_t *, hipStream_t);
+int reorder_state(int64_t n, const int32_t *perm, double *x, double *v, int32_t *ids, double *xref, double *vtmp,
+                  int32_t *itmp, const md_box_t *box, uint32_t *xs, hipStream_t s);
 int build_neighbors(const md_grid_t *, int64_t, const double *, const int32_t *, int32_t, int32_t *, int32_t *,
                     int32_t *, int32_t *, void *, const WsLayout &, hipStream_t);
 int forces_lj(const md_box_t *, int64_t, const double *, const uint32_t *, int32_t, const int32_t *, const int32_t *,

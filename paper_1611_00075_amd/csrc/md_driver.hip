@@ -83,18 +83,14 @@ int read_flag(md_system_t *sys, int32_t *host_dev, int32_t tag, hipStream_t s, b
 int rebuild(md_system_t *sys, const WsLayout &w, hipStream_t s, int32_t *host_dev)
 {
     const int64_t n = sys->n;
-    const size_t b3 = size_t(3 * n) * sizeof(double);
     int rc = bin_cells(&sys->grid, n, sys->x, sys->cell, sys->perm, sys->cell_start, sys->ws, w, s);
     if (rc) return rc;
     if (n > 0) {
-        MD_HIP_TRY(hipMemcpyAsync(sys->scratch, sys->x, b3, hipMemcpyDeviceToDevice, s));
-        if ((rc = permute(n, 3, sys->perm, sys->scratch, sys->x, 8, s))) return rc;
-        MD_HIP_TRY(hipMemcpyAsync(sys->scratch, sys->v, b3, hipMemcpyDeviceToDevice, s));
-        if ((rc = permute(n, 3, sys->perm, sys->scratch, sys->v, 8, s))) return rc;
-        MD_HIP_TRY(hipMemcpyAsync(sys->ids_scratch, sys->ids, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
-        if ((rc = permute(n, 1, sys->perm, sys->ids_scratch, sys->ids, 4, s))) return rc;
-        MD_HIP_TRY(hipMemcpyAsync(sys->xref, sys->x, b3, hipMemcpyDeviceToDevice, s));
-        if (!(sys->flags & MD_PAIR_FP64) && (rc = scale_positions(&sys->box, n, sys->x, sys->xs, s))) return rc;
+        // state into the sorted order; xref = the sorted positions
+        uint32_t *xs = (sys->flags & MD_PAIR_FP64) ? nullptr : sys->xs;
+        if ((rc = reorder_state(n, sys->perm, sys->x, sys->v, sys->ids, sys->xref, sys->scratch, sys->ids_scratch,
+                                &sys->box, xs, s)))
+            return rc;
         if (sys->potential == MD_POT_TBM) {
             // elements follow their atoms into the new order and into the scaled coordinates
             MD_HIP_TRY(hipMemcpyAsync(sys->types_scratch, sys->types, size_t(n) * 4, hipMemcpyDeviceToDevice, s));

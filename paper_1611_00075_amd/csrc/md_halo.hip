@@ -888,12 +888,13 @@ int md_dd_run(md_dd_t *dd, int64_t steps, double dt, double accel, double skin, 
 int md_dd_release(md_dd_t *dd)
 {
     if (!dd) return MD_ERR_ARG;
+    int rc = MD_OK;
     for (int q = 0; q < 4; ++q)
         if (dd->events[q]) {
-            hipEventDestroy(static_cast<hipEvent_t>(dd->events[q]));
+            if (hipEventDestroy(static_cast<hipEvent_t>(dd->events[q])) != hipSuccess) rc = MD_ERR_HIP;
             dd->events[q] = nullptr;
         }
-    return MD_OK;
+    return rc;
 }
 
 }  // extern "C"
