@@ -277,6 +277,30 @@ def jitter(sys: System, sigma: float, seed: int) -> System:
     return dataclasses.replace(sys, x=x, meta=dict(sys.meta, jitter=sigma))
 
 
+def graded(ncell: int, a: float, jit: float, seed: int, n_gas: int = 60, gas_sep: float = 2.0) -> tuple:
+    """fcc sites (ncell^3 cells of edge a) with site i kept with probability
+    2 |1 - 2 x_i / L| - 1 (clipped to [0, 1]) along the first axis, then
+    Gaussian noise of width jit: the local density falls from the lattice's
+    at the (periodic) box face to zero over a quarter of the box; the empty
+    middle half holds n_gas random atoms (x in [0.3 L, 0.7 L], no two closer
+    than gas_sep).  The neighbour counts thus take every value from 0 to the
+    full lattice's.  Returns (positions, box)."""
+    x = fcc_sites(ncell, ncell, ncell, a)
+    L = np.full(3, ncell * a)
+    rng = rng_for(seed, "graded")
+    keep = rng.uniform(0.0, 1.0, size=len(x)) < 2.0 * np.abs(1.0 - 2.0 * x[:, 0] / L[0]) - 1.0
+    x = x[keep] + rng.normal(0.0, jit, size=(int(keep.sum()), 3))
+    gas = []
+    while len(gas) < n_gas:
+        p = rng.uniform(0.0, 1.0, size=3) * L
+        p[0] = L[0] * (0.3 + 0.4 * p[0] / L[0])
+        d = np.array(gas) - p if gas else np.zeros((0, 3))
+        d -= L * np.round(d / L)
+        if not len(gas) or float(np.min(np.sum(d * d, axis=1))) >= gas_sep * gas_sep:
+            gas.append(p)
+    return np.concatenate([x, np.array(gas).reshape(-1, 3)]), L
+
+
 def random_gas(n: int, L, seed: int, min_dist: float = 0.0) -> np.ndarray:
     """n uniform random points in a box (optionally rejecting points closer
     than min_dist to an earlier point, by periodic distance)."""
