@@ -238,12 +238,26 @@ __device__ __forceinline__ SliceBufs slice_bufs(const void *xs, int64_t n_xs, co
     return {make_rsrc(xs, uint32_t(n_xs) * 16u), make_rsrc(idx + slice * cap * kSlice, uint32_t(cap) * 32u)};
 }
 
-// The 8 lanes of one atom are consecutive: combine over them in FP64.
+// A double from the lane that data-parallel-primitive control CTRL names
+// (row and bank masks full): quad_perm 0xB1 = lane ^ 1, 0x4E = lane ^ 2,
+// row_half_mirror 0x141 = 7 - lane within each group of 8.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// The 8 lanes of one atom are consecutive: combine over them in FP64, the
+// pairwise order ((g0 + g1) + (g2 + g3)) + ((g4 + g5) + (g6 + g7)) in every
+// lane.  All lanes of the wave must be active.
 __device__ __forceinline__ double combine(float s, float c)
 {
     double g = double(s) - double(c);
-#pragma unroll
-    for (int o = 1; o < kSlice; o <<= 1) g += __shfl_xor(g, o, kWave);
+    g += dpp_double<0xb1>(g);
+    g += dpp_double<0x4e>(g);
+    g += dpp_double<0x141>(g);
     return g;
 }
 
