@@ -211,6 +211,7 @@ struct FS32 {
     Gate gate;
     static constexpr int kRhoWords = 3;   // words of a neighbour's scaled coordinates pass 1 reads
     static constexpr bool kSplit = true;  // row walk: full batches, then one masked tail batch
+    static constexpr int kRhoUnroll = 4;  // row entries per lane per batch in pass 1 (measured)
 };
 
 // Second-moment tight-binding form: psi = exp2(cq - kq r) S(r),
@@ -227,6 +228,7 @@ struct TB32 {
     Gate gate;
     static constexpr int kRhoWords = 3;
     static constexpr bool kSplit = true;
+    static constexpr int kRhoUnroll = 6;  // two exponentials per pair: deeper batches pay
 };
 
 // Two elements: the tight-binding constants per pair kind k = t_i + t_j
@@ -249,6 +251,7 @@ struct TBM32 {
     // whole batches without selects, slots past the row end masked in the
     // pair term: the longer pair terms favour fewer selects over fewer slots
     static constexpr bool kSplit = false;
+    static constexpr int kRhoUnroll = 4;
 };
 
 // ---- pair terms of the forms ------------------------------------------------
@@ -654,7 +657,7 @@ static void launch_eam(int passes, uint32_t gb, hipStream_t s, int64_t n, uint4 
                        const BrickTab *tab)
 {
     if (passes & 1)
-        hipLaunchKernelGGL((k_eam_rho<P, TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap,
+        hipLaunchKernelGGL((k_eam_rho<P, TPA, P::kRhoUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap,
                            l.idx, l.cnt, p, rho, fprime, part1, sp, tab);
     if (passes & 2)
         hipLaunchKernelGGL((k_eam_force<P, TPA, kUnroll, CUBIC, E, C>), dim3(gb), dim3(kBlock), 0, s, n, q, l.cap,
