@@ -228,7 +228,7 @@ struct TB32 {
     Gate gate;
     static constexpr int kRhoWords = 3;
     static constexpr bool kSplit = true;
-    static constexpr int kRhoUnroll = 6;  // two exponentials per pair: deeper batches pay
+    static constexpr int kRhoUnroll = 6;  // exponentials per pair: deeper batches pay (measured)
 };
 
 // Two elements: the tight-binding constants per pair kind k = t_i + t_j
@@ -251,7 +251,7 @@ struct TBM32 {
     // whole batches without selects, slots past the row end masked in the
     // pair term: the longer pair terms favour fewer selects over fewer slots
     static constexpr bool kSplit = false;
-    static constexpr int kRhoUnroll = 4;
+    static constexpr int kRhoUnroll = 6;
 };
 
 // ---- pair terms of the forms ------------------------------------------------
