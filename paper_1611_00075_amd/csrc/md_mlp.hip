@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_desc(int64_t n, MlpArgs p, const
     const int32_t cnt = live ? min(count[i], cap) : 0;
     const uint4 pi = live ? xs[i] : make_uint4(0, 0, 0, 0);
     float *seg = seg_lds + (threadIdx.x / kSlice) * cap;
-    const int32_t nin = descriptor<2>(p, xs, live ? ell_row(idx, i, cap) : idx, cnt, pi, sub, lane, seg,
+    const int32_t nin = descriptor<6>(p, xs, live ? ell_row(idx, i, cap) : idx, cnt, pi, sub, lane, seg,
                                       idx_in && live ? idx_in + (ell_row(idx_in, i, cap) - idx_in) : nullptr, g);
     if (cnt_in && live && sub == 0) cnt_in[i] = nin;
     float v0, v1;
