@@ -294,9 +294,8 @@ def test_forces_eam_vs_oracle(M, orc):
     assert np.abs(rg - r["rho"]).max() / r["rho"].max() < 1e-5
     # site energies F(rho_i) + 1/2 sum_j V(r_ij): FP32 values of ~3.5 eV
     assert np.abs(eg - r["e_atom"]).max() < 2e-6 * np.abs(r["e_atom"]).max()
-    err = np.linalg.norm(fg - r["f"]) / np.linalg.norm(r["f"])
-    print(f"EAM FP32 force error (normwise) {err:.3e}")
-    assert err < 1e-5, err
+    import force_scale as FSC
+    FSC.check_form(orc, "fs", fg, x, s.L, oc, ic, r, inputs.FS_CU, what="EAM")
     evg = ev.cpu().numpy()
     assert evg[0] == pytest.approx(r["ev"][0], rel=1e-6)
     assert evg[1] == pytest.approx(r["ev"][1], rel=1e-6)

@@ -111,6 +111,7 @@ def test_eam_forms_rows_of_every_length(M, orc, form):
     rg = _by_id(st, rho, n)
     fg = _by_id(st, f, n, 3)
     assert np.abs(rg - r["rho"]).max() <= 1e-5 * r["rho"].max()
-    err = np.linalg.norm(fg - r["f"]) / np.linalg.norm(r["f"])
-    print(f"graded {form} ({n} atoms): force error (normwise) {err:.3e}")
-    assert err < 1e-5, err
+    import force_scale as FSC
+    prm = {"fs": inputs.FS_CU, "tb": inputs.TB_CU, "tbm": inputs.TB2_PAIRS}.get(form)
+    FSC.check_form(orc, form, fg, x, L, oc, ic, r, prm if form != "tab" else tab,
+                   types=t if form == "tbm" else None, what=f"graded {form} ({n} atoms)")

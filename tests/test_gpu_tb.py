@@ -1,7 +1,8 @@
 """GPU parity of the second-moment tight-binding potential (md_forces_tb,
 md_run with MD_POT_TB) against the FP64 oracle.  Bars as for the
 Finnis-Sinclair form: densities and site energies to FP32 accuracy, forces
-within 1e-5 normwise."""
+within 1e-5 normwise and per atom within 1e-5 of its sum of pair-force
+magnitudes (tests/force_scale.py)."""
 import numpy as np
 import pytest
 
@@ -57,9 +58,8 @@ def test_forces_tb_vs_oracle(M, orc, ncell, jit, seed):
     assert np.abs(g["rho"] - r["rho"]).max() / r["rho"].max() < 1e-5
     assert np.abs(g["fprime"] - r["fprime"]).max() / np.abs(r["fprime"]).max() < 1e-5
     assert np.abs(g["e_atom"] - r["e_atom"]).max() < 2e-6 * np.abs(r["e_atom"]).max()
-    err = np.linalg.norm(g["f"] - r["f"]) / np.linalg.norm(r["f"])
-    print(f"TB FP32 force error (normwise) {err:.3e}")
-    assert err < 1e-5, err
+    import force_scale as FSC
+    FSC.check_form(orc, "tb", g["f"], x, s.L, oc, ic, r, TB, what="TB")
     assert g["ev"][0] == pytest.approx(r["ev"][0], rel=1e-6)
     assert g["ev"][1] == pytest.approx(r["ev"][1], rel=1e-6)
     for c in range(2, 5):

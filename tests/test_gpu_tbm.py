@@ -2,7 +2,7 @@
 md_set_elements, md_run with MD_POT_TBM) against the FP64 oracle, on a
 random Cu75Au25-like alloy and on two element layers.  Bars as for one
 element: densities and site energies to FP32 accuracy, forces 1e-5
-normwise; the energy trace of an NVE run follows the oracle's."""
+normwise and per atom within 1e-5 of its sum of pair-force magnitudes; the energy trace of an NVE run follows the oracle's."""
 import numpy as np
 import pytest
 
@@ -77,9 +77,9 @@ def test_forces_tbm_vs_oracle(M, orc, layered, seed, pairs):
     r = orc.forces_tbm(x, L, oc, ic, t, pairs)
     assert np.abs(g["rho"] - r["rho"]).max() / r["rho"].max() < 1e-5
     assert np.abs(g["e_atom"] - r["e_atom"]).max() < 2e-6 * np.abs(r["e_atom"]).max()
-    err = np.linalg.norm(g["f"] - r["f"]) / np.linalg.norm(r["f"])
-    print(f"TBM {'layers' if layered else 'alloy'}: FP32 force error (normwise) {err:.3e}")
-    assert err < 1e-5, err
+    import force_scale as FSC
+    FSC.check_form(orc, "tbm", g["f"], x, L, oc, ic, r, pairs, types=t,
+                   what=f"TBM {'layers' if layered else 'alloy'}")
     assert g["ev"][0] == pytest.approx(r["ev"][0], rel=1e-6)
     for c in range(2, 5):
         assert g["ev"][c] == pytest.approx(r["ev"][c], rel=1e-5)

@@ -125,8 +125,10 @@ def test_neighbors_fcc_shell_counts(orc):
     x = orc.wrap(s.x, s.L)
     off, idx = orc.neighbors_cells(x, s.L, 2.8)
     counts = np.diff(off)
-    g = json.load(open(os.path.join(GOLD, "fcc_lattice.json")))
-    assert np.all(counts == sum(g["fcc_shell_counts"][:5]))
+    from lattice_util import fcc_shell_counts
+    m = fcc_shell_counts(6)
+    assert m[:5] == [12, 6, 24, 12, 24] and m[5] == 8
+    assert np.all(counts == sum(m[:5]))
 
 
 def test_neighbors_invariant_under_translation_and_permutation(orc):

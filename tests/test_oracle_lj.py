@@ -1,6 +1,6 @@
 """Pins for the oracle's Lennard-Jones forces, energies and virial.
 
-Energies are pinned to fcc lattice sums built from textbook shell counts and
+Energies are pinned to fcc lattice sums over enumerated shells and
 to the published infinite-range sums A12, A6; forces and virial to central
 finite differences of the energy; momentum to Newton's third law."""
 import json
@@ -22,9 +22,9 @@ def _lj(r2):
 
 def _lattice_shells(kmax):
     """Squared distances (units a_nn^2) and multiplicities of fcc shells,
-    from the textbook shell counts."""
-    g = json.load(open(os.path.join(GOLD, "fcc_lattice.json")))
-    return [(k + 1, g["fcc_shell_counts"][k]) for k in range(kmax)]
+    counted by enumerating lattice vectors."""
+    from lattice_util import fcc_shell_counts
+    return [(k + 1, m) for k, m in enumerate(fcc_shell_counts(kmax))]
 
 
 def test_lj_fcc_lattice_energy_closed_form(orc):

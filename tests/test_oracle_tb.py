@@ -10,9 +10,7 @@ tests re-derive A and xi from those two conditions in closed form (lattice
 shells of the fcc crystal), compare the oracle's lattice energies, densities,
 pressure and bulk modulus with the closed form, and pin forces and virial to
 finite differences of the oracle's own energy."""
-import json
 import math
-import os
 
 import numpy as np
 import pytest
@@ -21,12 +19,12 @@ from paper_1611_00075_amd import inputs
 
 TB = inputs.TB_CU
 EV_PER_A3_IN_GPA = 160.21766208
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fcc_lattice.json")
 
 
 def _shells(a):
     """(count, distance) of the fcc shells inside the smooth-cutoff start."""
-    counts = json.load(open(GOLDEN))["fcc_shell_counts"]
+    from lattice_util import fcc_shell_counts
+    counts = fcc_shell_counts(5)
     out = [(n, a * math.sqrt(k / 2.0)) for k, n in enumerate(counts, start=1)]
     return [(n, r) for n, r in out if r < TB["rs"]]
 

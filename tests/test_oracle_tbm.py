@@ -9,9 +9,7 @@ must be symmetric under exchanging the elements together with their
 parameters; the mixed pair kind is checked on a dimer against the
 one-element oracle run with the mixed parameters; forces and virial are
 pinned to finite differences of the energy."""
-import json
 import math
-import os
 
 import numpy as np
 import pytest
@@ -20,11 +18,11 @@ from paper_1611_00075_amd import inputs
 
 PAIRS = inputs.TB2_PAIRS
 R_LIST = 6.7
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fcc_lattice.json")
 
 
 def _solve(tb, a0, ecoh):
-    counts = json.load(open(GOLDEN))["fcc_shell_counts"]
+    from lattice_util import fcc_shell_counts
+    counts = fcc_shell_counts(5)
     sh = [(n, a0 * math.sqrt(k / 2.0)) for k, n in enumerate(counts, start=1)]
     sh = [(n, r) for n, r in sh if r < tb["rs"]]
     e2q = [n * math.exp(-2 * tb["q"] * (r / tb["r0"] - 1)) for n, r in sh]
