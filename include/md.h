@@ -189,6 +189,30 @@ int md_forces_lj(const md_box_t *box, int64_t n, const double *x,
                  const int32_t *count, const md_lj_t *lj, void *f, double *ev,
                  int32_t flags, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- allocation-free variant ----
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * kernels, arguments, outputs and errors as md_forces_lj, without the
+ * workspace: the per-block energy and virial partials (MD_ENERGY) live in a
+ * device array of the library, MD_NOALLOC_MAX_ATOMS / 32 rows of 8 doubles
+ * (8 MiB), one copy per GPU held until the process ends.  With MD_ENERGY,
+ * n > MD_NOALLOC_MAX_ATOMS is rejected with MD_ERR_ARG; without it any n
+ * md_forces_lj takes is accepted (the array is then not touched).  The call
+ * allocates and frees nothing; its first call on a device looks up that
+ * device's copy of the array.  `stream` must belong to the current device.
+ * All calls on one GPU share its array: calls with MD_ENERGY whose
+ * execution overlaps on that GPU (different streams, threads) race on it
+ * and must be serialised by the caller.  Nothing in the array needs to start
+ * at zero: each call writes every row it reads. */
+#define MD_NOALLOC_MAX_ATOMS (1 << 22)
+
+int md_forces_lj_noalloc(const md_box_t *box, int64_t n, const double *x,
+                         const uint32_t *xs, int32_t row_cap,
+                         const int32_t *idx, const int32_t *count,
+                         const md_lj_t *lj, void *f, double *ev,
+                         int32_t flags, void *stream);
+
 /* ---- steps a5/a6: embedded-atom method ---- */
 
 /* Finnis-Sinclair form of Eqs. (1)-(2): psi(r) = (r-d)^2 for r < d,

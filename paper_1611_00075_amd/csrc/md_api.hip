@@ -76,6 +76,23 @@ uint64_t spread3(uint64_t v)
 
 }  // namespace
 
+int md::lj_args_check(const md_box_t *box, int64_t n, const double *x, const uint32_t *xs, int32_t row_cap,
+                      const int32_t *idx, const int32_t *count, const md_lj_t *lj, const void *f, const double *ev,
+                      int32_t flags)
+{
+    if (!box_ok(box)) return MD_ERR_BOX;
+    if (!lj || !(lj->rc > 0.0) || !(lj->sigma > 0.0) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8 ||
+        row_cap > MD_MAX_ROW_CAP)
+        return MD_ERR_ARG;
+    if (flags & ~(MD_ENERGY | MD_PAIR_FP64 | MD_NO_COMPENSATE)) return MD_ERR_ARG;
+    if (n > 0 && (!idx || !count || !f)) return MD_ERR_ARG;
+    if (n > 0 && (flags & MD_PAIR_FP64) && !x) return MD_ERR_ARG;
+    if (n > 0 && !(flags & MD_PAIR_FP64) && !xs) return MD_ERR_ARG;
+    if (!(flags & MD_PAIR_FP64) && n > kMaxAtomsXs) return MD_ERR_ARG;
+    if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
+    return MD_OK;
+}
+
 extern "C" {
 
 const char *md_error_string(int status)
@@ -234,16 +251,7 @@ int md_forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t
                  const int32_t *idx, const int32_t *count, const md_lj_t *lj, void *f, double *ev, int32_t flags,
                  void *ws, size_t ws_bytes, void *stream)
 {
-    if (!box_ok(box)) return MD_ERR_BOX;
-    if (!lj || !(lj->rc > 0.0) || !(lj->sigma > 0.0) || n < 0 || n > kMaxAtoms || row_cap < 1 || row_cap % 8 ||
-        row_cap > MD_MAX_ROW_CAP)
-        return MD_ERR_ARG;
-    if (flags & ~(MD_ENERGY | MD_PAIR_FP64 | MD_NO_COMPENSATE)) return MD_ERR_ARG;
-    if (n > 0 && (!idx || !count || !f)) return MD_ERR_ARG;
-    if (n > 0 && (flags & MD_PAIR_FP64) && !x) return MD_ERR_ARG;
-    if (n > 0 && !(flags & MD_PAIR_FP64) && !xs) return MD_ERR_ARG;
-    if (!(flags & MD_PAIR_FP64) && n > kMaxAtomsXs) return MD_ERR_ARG;
-    if ((flags & MD_ENERGY) && !ev) return MD_ERR_ARG;
+    if (int rc = lj_args_check(box, n, x, xs, row_cap, idx, count, lj, f, ev, flags)) return rc;
     WsLayout w;
     if (int rc = ws_check_n(n, ws, ws_bytes, w)) return rc;
     return forces_lj(box, n, x, xs, row_cap, idx, count, lj, f, ev, flags, ws, w, as_stream(stream));

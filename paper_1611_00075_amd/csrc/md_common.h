@@ -151,6 +151,14 @@ int build_neighbors(const md_grid_t *, int64_t, const double *, const int32_t *,
                     int32_t *, int32_t *, void *, const WsLayout &, hipStream_t);
 int forces_lj(const md_box_t *, int64_t, const double *, const uint32_t *, int32_t, const int32_t *, const int32_t *,
               const md_lj_t *, void *, double *, int32_t, void *, const WsLayout &, hipStream_t, Gate = {});
+// forces_lj with its per-block energy partials (8 doubles per block of
+// kBlock / kSlice atoms, part_rows blocks at most) at `part`
+int forces_lj_part(const md_box_t *, int64_t, const double *, const uint32_t *, int32_t, const int32_t *,
+                   const int32_t *, const md_lj_t *, void *, double *, int32_t, double *, int64_t, hipStream_t,
+                   Gate = {});
+// argument checks of md_forces_lj (everything but the workspace)
+int lj_args_check(const md_box_t *, int64_t, const double *, const uint32_t *, int32_t, const int32_t *,
+                  const int32_t *, const md_lj_t *, const void *, const double *, int32_t);
 int forces_eam(const md_box_t *, int64_t, uint32_t *, int32_t, const int32_t *, const int32_t *, const md_fs_t *,
                float *, float *, float *, float *, double *, int32_t, void *, const WsLayout &, hipStream_t,
                Gate = {});

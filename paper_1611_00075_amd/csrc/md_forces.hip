@@ -604,9 +604,16 @@ int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *x
               const int32_t *cnt, const md_lj_t *lj, void *f, double *ev, int32_t flags, void *ws, const WsLayout &w,
               hipStream_t s, Gate gate)
 {
+    return forces_lj_part(box, n, x, xs, cap, idx, cnt, lj, f, ev, flags, ws_ptr<double>(ws, w.red1), w.red_blocks,
+                          s, gate);
+}
+
+int forces_lj_part(const md_box_t *box, int64_t n, const double *x, const uint32_t *xs, int32_t cap,
+                   const int32_t *idx, const int32_t *cnt, const md_lj_t *lj, void *f, double *ev, int32_t flags,
+                   double *part, int64_t part_rows, hipStream_t s, Gate gate)
+{
     const List l{cap, idx, cnt};
     const bool energy = flags & MD_ENERGY;
-    double *part = ws_ptr<double>(ws, w.red1);
     const double phi_rc = [&] {
         const double s2 = lj->sigma * lj->sigma / (lj->rc * lj->rc);
         const double s6 = s2 * s2 * s2;
@@ -616,7 +623,7 @@ int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *x
     if (n > 0) {
         if (flags & MD_PAIR_FP64) {
             gb = blocks_for(n, kTPA);
-            if (int64_t(gb) > w.red_blocks) return MD_ERR_WORKSPACE;
+            if (energy && int64_t(gb) > part_rows) return MD_ERR_WORKSPACE;
             LJ64 p;
             for (int a = 0; a < 3; ++a) {
                 p.L[a] = box->L[a];
@@ -637,7 +644,7 @@ int forces_lj(const md_box_t *box, int64_t n, const double *x, const uint32_t *x
         } else {
             const bool cubic = is_cubic(box);
             gb = blocks_for(n, kTPA);
-            if (int64_t(gb) > w.red_blocks) return MD_ERR_WORKSPACE;
+            if (energy && int64_t(gb) > part_rows) return MD_ERR_WORKSPACE;
             const LJ32 p = lj_constants(box, lj, gate);
             const uint4 *q = reinterpret_cast<const uint4 *>(xs);
             float *ff = static_cast<float *>(f);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 MD_OK, MD_ERR_ARG, MD_ERR_BOX, MD_ERR_CAPACITY = 0, -1, -2, -3
 MD_ERR_NONFINITE, MD_ERR_HIP, MD_ERR_WORKSPACE = -4, -5, -6
+MD_NOALLOC_MAX_ATOMS = 1 << 22
 MD_ENERGY, MD_PAIR_FP64, MD_NO_COMPENSATE, MD_MLP_REUSE, MD_XS_ELEMENT = 0x1, 0x2, 0x4, 0x8, 0x10
 MD_KICK_DRIFT, MD_KICK = 1, 2
 MD_SLICE = 8
@@ -170,6 +171,8 @@ def lib():
                                          C.POINTER(C.c_int32), _vp, C.c_size_t, _vp]
         L.md_forces_lj.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, C.c_int32, _vp, _vp, C.POINTER(LJ),
                                    _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_forces_lj_noalloc.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, C.c_int32, _vp, _vp,
+                                           C.POINTER(LJ), _vp, _vp, C.c_int32, _vp]
         L.md_forces_eam.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(FS), _vp,
                                     _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
         L.md_forces_tb.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(TB), _vp,
@@ -332,6 +335,20 @@ def md_forces_lj(L, n: int, x, xs, row_cap: int, idx, count, lj: tuple, f, ev, f
                               _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"), _ptr(count, torch.int32, n, "count"),
                               C.byref(p), _ptr(f, fdt, 3 * n, "f"), _ptr(ev, torch.float64, 8, "ev"), int(flags),
                               _ptr(ws, name="ws"), ws.numel(), _stream(stream)), "md_forces_lj")
+
+
+def md_forces_lj_noalloc(L, n: int, x, xs, row_cap: int, idx, count, lj: tuple, f, ev, flags: int,
+                         stream=None):
+    """md_forces_lj without a workspace (the library's own per-GPU array)."""
+    import torch
+    fdt = torch.float64 if flags & MD_PAIR_FP64 else torch.float32
+    p = LJ(*[float(v) for v in lj])
+    _check(lib().md_forces_lj_noalloc(C.byref(box(L)), int(n), _ptr(x, torch.float64, 3 * n, "x"),
+                                      _ptr(xs, torch.int32, 4 * n, "xs"), int(row_cap),
+                                      _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"),
+                                      _ptr(count, torch.int32, n, "count"), C.byref(p), _ptr(f, fdt, 3 * n, "f"),
+                                      _ptr(ev, torch.float64, 8, "ev"), int(flags), _stream(stream)),
+           "md_forces_lj_noalloc")
 
 
 def md_forces_eam(L, n: int, xs, row_cap: int, idx, count, fs: dict, rho, fprime, f, ev, flags: int, ws,
