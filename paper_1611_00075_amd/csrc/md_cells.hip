@@ -261,29 +261,34 @@ int set_elements(int64_t n, const int32_t *types, uint32_t *xs, hipStream_t s)
 
 constexpr int kMaxStencil = 125;       // (2*reach+1)^3, reach <= 2
 
-// distinct values of (c + o) mod nc, o in [-reach, reach], in increasing o
-__device__ __forceinline__ int stencil_axis(int32_t c, int32_t nc, int32_t reach, int32_t *out)
+// Distinct values of (c + o) mod nc, o in [-reach, reach], in increasing o;
+// img[k] = floor((c + o) / nc) of the value's first offset: the periodic
+// image of that stencil cell (the only one when no value was de-duplicated).
+__device__ __forceinline__ int stencil_axis(int32_t c, int32_t nc, int32_t reach, int32_t *out, int32_t *img)
 {
     int m = 0;
     for (int o = -reach; o <= reach; ++o) {
-        int32_t v = c + o;
-        while (v < 0) v += nc;
-        while (v >= nc) v -= nc;
+        int32_t v = c + o, k = 0;
+        while (v < 0) {
+            v += nc;
+            --k;
+        }
+        while (v >= nc) {
+            v -= nc;
+            ++k;
+        }
         bool dup = false;
-        for (int k = 0; k < m; ++k) dup |= (out[k] == v);
-        if (!dup) out[m++] = v;
+        for (int q = 0; q < m; ++q) dup |= (out[q] == v);
+        if (!dup) {
+            img[m] = k;
+            out[m++] = v;
+        }
     }
     return m;
 }
 
 // Wave-uniform copies of values the compiler cannot prove uniform.
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ double lane_f64(double v, int l)
-{
-    const int64_t b = __double_as_longlong(v);
-    const int32_t lo = __builtin_amdgcn_readlane(int32_t(b), l), hi = __builtin_amdgcn_readlane(int32_t(b >> 32), l);
-    return __longlong_as_double((int64_t(hi) << 32) | int64_t(uint32_t(lo)));
-}
 
 // The definition's minimum image without branches: subtracting 0, L or -L
 // gives the same bits as leaving d alone, d - L or d + L.
@@ -293,15 +298,36 @@ __device__ __forceinline__ double minimg_sel(double d, double L, double hL)
     return d - t;
 }
 
-constexpr int kNbChunks = 4;           // 64-candidate chunks held in registers at once
-constexpr int kNbWaves = 1;            // wavefronts (cells) per block
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+constexpr int kNbChunks = 4;                   // 64-candidate chunks held in registers at once
+constexpr int kNbTile = kNbChunks * kWave;     // candidates per register tile
+constexpr int kNbStage = 2 * kNbTile;          // staged candidates: a tile plus one raw tile's survivors
+constexpr int kNbWaves = 1;                    // wavefronts (cells) per block
+constexpr int kNbMap = 1024;                   // candidates whose stencil cell is tabulated in LDS
 constexpr int kNbBlock = kNbWaves * kWave;
 
-// Per-wave LDS state: the stencil's cell ranges and the home atoms'
-// positions (read back as broadcasts).
+// Per-wave LDS state: the home atoms' positions (read back as broadcasts),
+// the stencil's cell ranges with their periodic images, and the candidates
+// that passed the bounding-box test, waiting for a register tile.
 struct NbWaveLds {
     double hx[kWave], hy[kWave], hz[kWave];
-    int32_t rstart[kMaxStencil], rbase[kMaxStencil + 1];
+    double box[6];                            // homes' bounding box: lo x, y, z, hi x, y, z
+    int32_t rstart[kMaxStencil], rbase[kMaxStencil + 1], rimg[kMaxStencil];
+    int32_t stage[kNbStage];
+    uint8_t cmap[kNbMap];                     // stencil cell of each candidate (up to kNbMap)
 };
 
 // A tile of candidates in registers: lane l holds candidates l, 64 + l, ...
@@ -313,8 +339,9 @@ struct NbTile {
 // Home atom i (position xi, yi, zi; r entries so far) against the first NC
 // chunks of the tile: every hit is appended to the row at r in candidate
 // order; returns the new row length.  All chunks are tested before any is
-// stored, so the NC chains are independent; a lane without a hit stores to
-// an offset past the row's buffer, which drops the store.
+// stored, so the NC chains are independent; only lanes with a hit store,
+// through a buffer whose range ends at the row capacity (stores past it are
+// dropped).
 template <int NC, bool INTERIOR>
 __device__ __forceinline__ uint32_t nb_home(const NbTile &T, double xi, double yi, double zi, int32_t i, uint32_t r,
                                             __amdgpu_buffer_rsrc_t row, double rl2, const GridArgs &g)
@@ -339,19 +366,26 @@ __device__ __forceinline__ uint32_t nb_home(const NbTile &T, double xi, double y
         const uint32_t e = __builtin_amdgcn_mbcnt_hi(uint32_t(mk[c] >> 32),
                                                      __builtin_amdgcn_mbcnt_lo(uint32_t(mk[c]), r));
         // entry e of the row at byte (e / 8) * 256 + (e % 8) * 4
-        const uint32_t off = hit[c] ? (e << 2) + __umul24(e >> 3, 224u) : 0xfffffff0u;
-        __builtin_amdgcn_raw_buffer_store_b32(T.j[c], row, off, 0, 0);
+        if (hit[c]) __builtin_amdgcn_raw_buffer_store_b32(T.j[c], row, (e << 2) + __umul24(e >> 3, 224u), 0, 0);
         r += uint32_t(__popcll(mk[c]));
     }
     return r;
 }
 
-// The home batches of one cell against its stencil's candidates (tile by
-// tile); returns the longest row of the cell.
+// The home batches of one cell against its stencil's candidates; returns the
+// longest row of the cell.
+//
+// Candidates are streamed 256 at a time from the stencil's cell ranges.  With
+// `filter`, a candidate is kept only if it lies within r_list of the
+// bounding box of the batch's home atoms (in its periodic image of the
+// stencil; with a margin of 1e-9 of r_list^2, far above the rounding of
+// either test, so no candidate that the exact test accepts is dropped).
+// Kept candidates are staged in LDS; every 256 of them fill a register
+// tile, against which each home atom is tested with the exact FP64 test.
 template <bool INTERIOR>
 __device__ __forceinline__ int32_t nb_cell(NbWaveLds &L, int64_t n, const double *x, const GridArgs &g, double rl2,
-                                           int32_t h0, int32_t h1, int32_t m, int32_t total, int32_t row_cap,
-                                           int32_t *idx, int32_t *count)
+                                           double keep2, bool filter, int32_t h0, int32_t h1, int32_t m,
+                                           int32_t total, int32_t row_cap, int32_t *idx, int32_t *count)
 {
     const int lane = threadIdx.x % kWave;
     int top = 1;                              // highest power of two <= m
@@ -364,50 +398,119 @@ __device__ __forceinline__ int32_t nb_cell(NbWaveLds &L, int64_t n, const double
     for (int32_t hb = h0; hb < h1; hb += kWave) {
         const int32_t hn = min(kWave, h1 - hb);
         const int32_t hl = hb + min(lane, hn - 1);
-        L.hx[lane] = x[hl];
-        L.hy[lane] = x[n + hl];
-        L.hz[lane] = x[2 * n + hl];
+        const double xh = x[hl], yh = x[n + hl], zh = x[2 * n + hl];
+        L.hx[lane] = xh;
+        L.hy[lane] = yh;
+        L.hz[lane] = zh;
+        // bounding box of the batch's homes (lanes past hn repeat the last home)
+        if (filter) {
+            const double b0 = wave_min(xh), b1 = wave_min(yh), b2 = wave_min(zh);
+            const double b3 = wave_max(xh), b4 = wave_max(yh), b5 = wave_max(zh);
+            if (lane == 0) {
+                L.box[0] = b0, L.box[1] = b1, L.box[2] = b2;
+                L.box[3] = b3, L.box[4] = b4, L.box[5] = b5;
+            }
+        }
         // first int32 of the lane's home row (slice block + position in the slice)
         const int64_t row_l = int64_t(hl >> 3) * row_cap * 8 + (hl & 7) * 8;
         wave_sync();
         int32_t run_l = 0;                                // row length of home atom `lane`
-        for (int32_t t0 = 0; t0 < total; t0 += kNbChunks * kWave) {
-            const int nch = min(kNbChunks, (total - t0 + kWave - 1) / kWave);
-            NbTile T;
+        int32_t fill = 0;                                 // staged candidates (wave-uniform)
+        for (int32_t t0 = 0; t0 < total; t0 += kNbTile) {
+            // a raw tile of up to 256 candidates, four independent chunks
+            bool keep[kNbChunks];
+            int32_t jr[kNbChunks];
 #pragma unroll
             for (int c = 0; c < kNbChunks; ++c) {
                 const int32_t gq = t0 + c * kWave + lane;
-                T.j[c] = -1;
-                T.x[c] = T.y[c] = T.z[c] = inf;
-                if (c < nch && gq < total) {
-                    // last range k with rbase[k] <= gq; rbase[m] = total never is
+                keep[c] = false;
+                jr[c] = 0;
+                if (gq < total) {
+                    // the stencil cell k of candidate gq: tabulated, or the last
+                    // range with rbase[k] <= gq (rbase[m] = total never is)
                     int k = 0;
-                    for (int s = top; s > 0; s >>= 1) {
-                        const int t = min(k + s, m);
-                        k = L.rbase[t] <= gq ? t : k;
+                    if (total <= kNbMap) {
+                        k = L.cmap[gq];
+                    } else {
+                        for (int s = top; s > 0; s >>= 1) {
+                            const int t = min(k + s, m);
+                            k = L.rbase[t] <= gq ? t : k;
+                        }
                     }
                     const int32_t j = L.rstart[k] + (gq - L.rbase[k]);
-                    T.j[c] = j;
-                    T.x[c] = x[j];
-                    T.y[c] = x[n + j];
-                    T.z[c] = x[2 * n + j];
+                    jr[c] = j;
+                    keep[c] = true;
+                    if (filter) {
+                        double cx = x[j], cy = x[n + j], cz = x[2 * n + j];
+                        if (!INTERIOR) {
+                            const int32_t im = L.rimg[k];
+                            cx += double((im & 3) - 1) * g.L[0];
+                            cy += double(((im >> 2) & 3) - 1) * g.L[1];
+                            cz += double(((im >> 4) & 3) - 1) * g.L[2];
+                        }
+                        const double dx = fmax(fmax(L.box[0] - cx, cx - L.box[3]), 0.0);
+                        const double dy = fmax(fmax(L.box[1] - cy, cy - L.box[4]), 0.0);
+                        const double dz = fmax(fmax(L.box[2] - cz, cz - L.box[5]), 0.0);
+                        keep[c] = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)) < keep2;
+                    }
                 }
             }
-            for (int32_t h = 0; h < hn; ++h) {
-                const int32_t i = hb + h;
-                const uint32_t r = uint32_t(__builtin_amdgcn_readlane(run_l, h));
-                const int64_t ro = int64_t(uint32_t(__builtin_amdgcn_readlane(int32_t(row_l), h))) |
-                                   (int64_t(__builtin_amdgcn_readlane(int32_t(row_l >> 32), h)) << 32);
-                const auto row = make_rsrc(idx + ro, row_bytes);
-                const double xi = L.hx[h], yi = L.hy[h], zi = L.hz[h];
-                uint32_t rn;
-                switch (nch) {
-                case 4: rn = nb_home<4, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
-                case 3: rn = nb_home<3, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
-                case 2: rn = nb_home<2, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
-                default: rn = nb_home<1, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
+#pragma unroll
+            for (int c = 0; c < kNbChunks; ++c) {
+                const uint64_t mk = __builtin_amdgcn_ballot_w64(keep[c]);
+                if (keep[c])
+                    L.stage[fill + int32_t(__builtin_amdgcn_mbcnt_hi(uint32_t(mk >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo(uint32_t(mk), 0u)))] =
+                        jr[c];
+                fill += __popcll(mk);
+            }
+            const bool last = t0 + kNbTile >= total;
+            while (fill >= kNbTile || (last && fill > 0)) {
+                wave_sync();
+                const int32_t nt = min(fill, kNbTile);
+                const int nch = (nt + kWave - 1) / kWave;
+                NbTile T;
+#pragma unroll
+                for (int c = 0; c < kNbChunks; ++c) {
+                    const int32_t q = c * kWave + lane;
+                    T.j[c] = -1;
+                    T.x[c] = T.y[c] = T.z[c] = inf;
+                    if (q < nt) {
+                        const int32_t jj = L.stage[q];
+                        T.j[c] = jj;
+                        T.x[c] = x[jj];
+                        T.y[c] = x[n + jj];
+                        T.z[c] = x[2 * n + jj];
+                    }
                 }
-                if (lane == h) run_l = int32_t(rn);
+                for (int32_t h = 0; h < hn; ++h) {
+                    const int32_t i = hb + h;
+                    const uint32_t r = uint32_t(__builtin_amdgcn_readlane(run_l, h));
+                    const int64_t ro = int64_t(uint32_t(__builtin_amdgcn_readlane(int32_t(row_l), h))) |
+                                       (int64_t(__builtin_amdgcn_readlane(int32_t(row_l >> 32), h)) << 32);
+                    const auto row = make_rsrc(idx + ro, row_bytes);
+                    const double xi = L.hx[h], yi = L.hy[h], zi = L.hz[h];
+                    uint32_t rn;
+                    switch (nch) {
+                    case 4: rn = nb_home<4, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
+                    case 3: rn = nb_home<3, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
+                    case 2: rn = nb_home<2, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
+                    default: rn = nb_home<1, INTERIOR>(T, xi, yi, zi, i, r, row, rl2, g); break;
+                    }
+                    if (lane == h) run_l = int32_t(rn);
+                }
+                // candidates staged past the tile move to the front
+                const int32_t left = fill - nt;
+                int32_t v[kNbChunks];
+#pragma unroll
+                for (int c = 0; c < kNbChunks; ++c)
+                    if (c * kWave + lane < left) v[c] = L.stage[nt + c * kWave + lane];
+                wave_sync();
+#pragma unroll
+                for (int c = 0; c < kNbChunks; ++c)
+                    if (c * kWave + lane < left) L.stage[c * kWave + lane] = v[c];
+                fill = left;
+                wave_sync();
             }
         }
         if (lane < hn) count[hb + lane] = run_l;
@@ -417,12 +520,12 @@ __device__ __forceinline__ int32_t nb_cell(NbWaveLds &L, int64_t n, const double
     return longest;
 }
 
-// One wavefront per cell (Morton rank), no block-wide barriers.  The atoms
-// of the up to 27 (125) neighbouring cells are contiguous runs of the
-// sorted arrays; the wave walks them in tiles of 256 candidates held in
-// registers (past the last candidate, candidates at infinity), and tests
-// one home atom against 64 candidates at a time, compacting hits with a
-// ballot straight into the sliced-ELL rows (entry e of atom i at
+// One wavefront per cell (Morton rank), several independent wavefronts per
+// block, no block-wide barriers.  The atoms of the up to 27 (125)
+// neighbouring cells are contiguous runs of the sorted arrays; the wave
+// streams them, keeps those within reach of its homes' bounding box, and
+// tests each home atom against 64 kept candidates at a time, compacting hits
+// with a ballot straight into the sliced-ELL rows (entry e of atom i at
 // idx[(i/8 * row_cap/8 + e/8) * 64 + (i%8) * 8 + e%8]).  Row order: stencil
 // cell, then sorted index.  Rows longer than row_cap are counted but
 // truncated (the row is written through a buffer whose range ends at entry
@@ -433,9 +536,12 @@ __device__ __forceinline__ int32_t nb_cell(NbWaveLds &L, int64_t n, const double
 // on every axis) use the plain difference x_j - x_i: every candidate is then
 // closer than half a box, so the minimum-image correction of the definition
 // never applies and the result is bitwise the same.  A padding candidate
-// gives +inf in every branch, so it never passes r^2 < r_list^2.
+// gives +inf in every branch, so it never passes r^2 < r_list^2.  The
+// bounding-box filter runs when no stencil offset was de-duplicated on any
+// axis (nc >= 2 reach + 1): each stencil cell is then one periodic image,
+// the only one that can lie within r_list of a home.
 __global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double *x, GridArgs g, double rl2,
-                                                        int64_t n_cells, const int32_t *cell_start,
+                                                        double keep2, int64_t n_cells, const int32_t *cell_start,
                                                         const int32_t *rank_xyz, const int32_t *lin2rank,
                                                         int32_t row_cap, int32_t *idx, int32_t *count,
                                                         int32_t *max_count)
@@ -452,13 +558,15 @@ __global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double 
     // their ranges, and a shuffle scan forms the range prefix
     const int32_t pk = uni(rank_xyz[rank]);   // packed cell coordinates
     const int32_t c3[3] = {pk & 1023, (pk >> 10) & 1023, pk >> 20};
-    bool interior = true;
-    for (int a = 0; a < 3; ++a)
+    bool interior = true, nodup = true;
+    for (int a = 0; a < 3; ++a) {
         interior &= (g.nc[a] >= 2 * g.reach + 2) && (c3[a] - g.reach >= 0) && (c3[a] + g.reach < g.nc[a]);
-    int32_t ax[5], ay[5], az[5];
-    const int mx = stencil_axis(c3[0], g.nc[0], g.reach, ax);
-    const int my = stencil_axis(c3[1], g.nc[1], g.reach, ay);
-    const int mz = stencil_axis(c3[2], g.nc[2], g.reach, az);
+        nodup &= g.nc[a] >= 2 * g.reach + 1;
+    }
+    int32_t ax[5], ay[5], az[5], ix[5], iy[5], iz[5];
+    const int mx = stencil_axis(c3[0], g.nc[0], g.reach, ax, ix);
+    const int my = stencil_axis(c3[1], g.nc[1], g.reach, ay, iy);
+    const int mz = stencil_axis(c3[2], g.nc[2], g.reach, az, iz);
     const int m = mx * my * mz;
     int32_t carry = 0;
     for (int t0 = 0; t0 < m; t0 += kWave) {
@@ -475,6 +583,7 @@ __global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double 
             const int32_t st = cell_start[r];
             len = cell_start[r + 1] - st;
             L.rstart[t] = st;
+            L.rimg[t] = (ix[a] + 1) | ((iy[b] + 1) << 2) | ((iz[c] + 1) << 4);
         }
         int32_t v = len;
 #pragma unroll
@@ -487,8 +596,12 @@ __global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double 
     }
     if (lane == 0) L.rbase[0] = 0;
     wave_sync();
-    int32_t longest = interior ? nb_cell<true>(L, n, x, g, rl2, h0, h1, m, carry, row_cap, idx, count)
-                               : nb_cell<false>(L, n, x, g, rl2, h0, h1, m, carry, row_cap, idx, count);
+    if (carry <= kNbMap)   // tabulate the stencil cell of every candidate: lane t writes cell t's run
+        for (int t = lane; t < m; t += kWave)
+            for (int32_t q = L.rbase[t], e = L.rbase[t + 1]; q < e; ++q) L.cmap[q] = uint8_t(t);
+    wave_sync();
+    int32_t longest = interior ? nb_cell<true>(L, n, x, g, rl2, keep2, nodup, h0, h1, m, carry, row_cap, idx, count)
+                               : nb_cell<false>(L, n, x, g, rl2, keep2, nodup, h0, h1, m, carry, row_cap, idx, count);
     for (int o = kWave / 2; o > 0; o >>= 1) longest = max(longest, __shfl_xor(longest, o, kWave));
     // *max_count only grows, so a wave whose longest row does not exceed a
     // value already there has nothing to add: the check keeps the atomics on
@@ -510,13 +623,14 @@ int build_neighbors(const md_grid_t *grid, int64_t n, const double *x, const int
     }
     g.reach = grid->reach;
     const double rl2 = grid->r_list * grid->r_list;
+    const double keep2 = rl2 * (1.0 + 1e-9);
     int rc = launch_fill_i32(max_count, 1, 0, s);
     if (rc) return rc;
     const uint32_t nb = uint32_t((grid->n_cells + kNbWaves - 1) / kNbWaves);
     if (n > 0) {
-        hipLaunchKernelGGL(k_neighbors, dim3(nb), dim3(kNbBlock), 0, s, n, x, g, rl2, grid->n_cells, cell_start,
-                           ws_ptr<int32_t>(ws, w.rank2lin), ws_ptr<int32_t>(ws, w.lin2rank), row_cap, idx, count,
-                           max_count);
+        hipLaunchKernelGGL(k_neighbors, dim3(nb), dim3(kNbBlock), 0, s, n, x, g, rl2, keep2, grid->n_cells,
+                           cell_start, ws_ptr<int32_t>(ws, w.rank2lin), ws_ptr<int32_t>(ws, w.lin2rank), row_cap, idx,
+                           count, max_count);
         MD_HIP_TRY(hipGetLastError());
     }
     if (needed) {
