@@ -59,7 +59,7 @@ class MDParams(C.Structure):
     _fields_ = [("potential", C.c_int32), ("lj", LJParams), ("fs", FSParams),
                 ("r_list", C.c_double), ("skin", C.c_double), ("dt", C.c_double),
                 ("mass", C.c_double), ("force_to_accel", C.c_double),
-                ("reverse_order", C.c_int32)]
+                ("reverse_order", C.c_int32), ("threads", C.c_int32)]
 
 
 POT_LJ, POT_EAM = 0, 1
@@ -75,6 +75,8 @@ def _declare(L):
         f.restype = C.c_int64
     L.or_forces_lj.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
                                C.POINTER(LJParams), _dp, _dp, _dp, _dp]
+    L.or_forces_lj_omp.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
+                                   C.POINTER(LJParams), _dp, _dp, _dp, _dp, C.c_int32]
     L.or_forces_eam.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
                                 C.POINTER(FSParams), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_forces_tb.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
@@ -162,6 +164,20 @@ def forces_lj(x, L, off, idx, eps=1.0, sigma=1.0, rc=2.5):
                        _p(np.ascontiguousarray(off, np.int64), _i64p),
                        _p(np.ascontiguousarray(idx, np.int32), _i32p), C.byref(prm),
                        *[_p(c) for c in f], _p(ev))
+    return np.stack(f, axis=1), ev
+
+
+def forces_lj_omp(x, L, off, idx, eps=1.0, sigma=1.0, rc=2.5, threads=2):
+    """forces_lj with the rows shared among OpenMP threads (timing aid)."""
+    xs = _soa(x)
+    n = len(xs[0])
+    f = [np.zeros(n) for _ in range(3)]
+    ev = np.zeros(8)
+    prm = LJParams(eps, sigma, rc)
+    lib().or_forces_lj_omp(n, _p(_box(L)), *[_p(c) for c in xs],
+                           _p(np.ascontiguousarray(off, np.int64), _i64p),
+                           _p(np.ascontiguousarray(idx, np.int32), _i32p), C.byref(prm),
+                           *[_p(c) for c in f], _p(ev), int(threads))
     return np.stack(f, axis=1), ev
 
 
@@ -261,9 +277,10 @@ def forces_tab(x, L, off, idx, tab):
 
 
 def md_run(x, v, L, steps, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None,
-           r_list, skin, dt, mass=1.0, force_to_accel=1.0, reverse_order=False):
+           r_list, skin, dt, mass=1.0, force_to_accel=1.0, reverse_order=False, threads=1):
     """Velocity-Verlet run.  Returns dict(x, v, epot[steps+1], ekin[steps+1],
-    builds, loop_seconds)."""
+    builds, loop_seconds).  threads > 1: LJ forces and the per-atom loops on
+    that many OpenMP threads (for timing)."""
     xs = _soa(x)
     vs = _soa(v)
     n = len(xs[0])
@@ -275,6 +292,7 @@ def md_run(x, v, L, steps, *, potential="lj", lj=(1.0, 1.0, 2.5), fs=None,
     prm.r_list, prm.skin, prm.dt = r_list, skin, dt
     prm.mass, prm.force_to_accel = mass, force_to_accel
     prm.reverse_order = 1 if reverse_order else 0
+    prm.threads = int(threads)
     ep = np.zeros(steps + 1)
     ek = np.zeros(steps + 1)
     secs = np.zeros(1)

@@ -176,7 +176,7 @@ int64_t or_neighbors_cells(int64_t n, const double L[3], double r_list,
 }
 
 /* ------------------------------------------------------------------ */
-/* Lennard-Jones: pair loop with Newton's third law                    */
+/* Lennard-Jones: forces as the gradient of the pair energy            */
 /* ------------------------------------------------------------------ */
 
 static double lj_phi(const or_lj_t *p, double r2)
@@ -184,6 +184,35 @@ static double lj_phi(const or_lj_t *p, double r2)
     double s2 = p->sigma * p->sigma / r2;
     double s6 = s2 * s2 * s2;
     return 4.0 * p->eps * (s6 * s6 - s6);
+}
+
+/* The contribution of atom i's row: its force, and its half of the energy
+ * and virial of each of its pairs (every pair appears in both rows). */
+static void lj_row(int64_t i, const double L[3], const double *x, const double *y, const double *z,
+                   const int64_t *offsets, const int32_t *idx, const or_lj_t *p, double rc2, double phi_rc,
+                   double f[3], double *E, double *Es, double W[6])
+{
+    f[0] = f[1] = f[2] = 0.0;
+    for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+        int64_t j = idx[k];
+        if (j == i) continue;
+        double d[3];
+        double r2 = dist2(L, x, y, z, i, j, d);
+        if (!(r2 < rc2)) continue;
+        /* R = r_i - r_j is minus the displacement i -> j */
+        double R[3] = {-d[0], -d[1], -d[2]};
+        double s2 = p->sigma * p->sigma / r2;
+        double s6 = s2 * s2 * s2;
+        /* -dPhi(r_ij)/dr_i = -(1/r) dPhi/dr R */
+        double fs = 24.0 * p->eps * (2.0 * s6 * s6 - s6) / r2;
+        f[0] += fs * R[0]; f[1] += fs * R[1]; f[2] += fs * R[2];
+        double phi = 4.0 * p->eps * (s6 * s6 - s6);
+        *E += 0.5 * phi;
+        *Es += 0.5 * (phi - phi_rc);
+        W[0] += 0.5 * fs * R[0] * R[0]; W[1] += 0.5 * fs * R[1] * R[1];
+        W[2] += 0.5 * fs * R[2] * R[2]; W[3] += 0.5 * fs * R[0] * R[1];
+        W[4] += 0.5 * fs * R[0] * R[2]; W[5] += 0.5 * fs * R[1] * R[2];
+    }
 }
 
 void or_forces_lj(int64_t n, const double L[3], const double *x,
@@ -194,32 +223,32 @@ void or_forces_lj(int64_t n, const double L[3], const double *x,
     const double rc2 = p->rc * p->rc;
     const double phi_rc = lj_phi(p, rc2);
     double E = 0.0, Es = 0.0, W[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t i = 0; i < n; ++i) fx[i] = fy[i] = fz[i] = 0.0;
     for (int64_t i = 0; i < n; ++i) {
-        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
-            int64_t j = idx[k];
-            if (j <= i) continue; /* each unordered pair once */
-            double d[3];
-            double r2 = dist2(L, x, y, z, i, j, d);
-            if (!(r2 < rc2)) continue;
-            /* R = r_i - r_j is minus the displacement i -> j */
-            double R[3] = {-d[0], -d[1], -d[2]};
-            double s2 = p->sigma * p->sigma / r2;
-            double s6 = s2 * s2 * s2;
-            /* -(1/r) dPhi/dr */
-            double fs = 24.0 * p->eps * (2.0 * s6 * s6 - s6) / r2;
-            fx[i] += fs * R[0]; fy[i] += fs * R[1]; fz[i] += fs * R[2];
-            fx[j] -= fs * R[0]; fy[j] -= fs * R[1]; fz[j] -= fs * R[2];
-            double phi = 4.0 * p->eps * (s6 * s6 - s6);
-            E += phi;
-            Es += phi - phi_rc;
-            W[0] += fs * R[0] * R[0]; W[1] += fs * R[1] * R[1];
-            W[2] += fs * R[2] * R[2]; W[3] += fs * R[0] * R[1];
-            W[4] += fs * R[0] * R[2]; W[5] += fs * R[1] * R[2];
-        }
+        double f[3];
+        lj_row(i, L, x, y, z, offsets, idx, p, rc2, phi_rc, f, &E, &Es, W);
+        fx[i] = f[0]; fy[i] = f[1]; fz[i] = f[2];
     }
     ev[0] = E; ev[1] = Es;
     for (int a = 0; a < 6; ++a) ev[2 + a] = W[a];
+}
+
+void or_forces_lj_omp(int64_t n, const double L[3], const double *x,
+                      const double *y, const double *z, const int64_t *offsets,
+                      const int32_t *idx, const or_lj_t *p, double *fx,
+                      double *fy, double *fz, double ev[8], int32_t threads)
+{
+    const double rc2 = p->rc * p->rc;
+    const double phi_rc = lj_phi(p, rc2);
+    double E = 0.0, Es = 0.0, W0 = 0, W1 = 0, W2 = 0, W3 = 0, W4 = 0, W5 = 0;
+#pragma omp parallel for num_threads(threads) schedule(static) reduction(+ : E, Es, W0, W1, W2, W3, W4, W5)
+    for (int64_t i = 0; i < n; ++i) {
+        double f[3], W[6] = {0, 0, 0, 0, 0, 0};
+        lj_row(i, L, x, y, z, offsets, idx, p, rc2, phi_rc, f, &E, &Es, W);
+        fx[i] = f[0]; fy[i] = f[1]; fz[i] = f[2];
+        W0 += W[0]; W1 += W[1]; W2 += W[2]; W3 += W[3]; W4 += W[4]; W5 += W[5];
+    }
+    ev[0] = E; ev[1] = Es;
+    ev[2] = W0; ev[3] = W1; ev[4] = W2; ev[5] = W3; ev[6] = W4; ev[7] = W5;
 }
 
 /* ------------------------------------------------------------------ */
@@ -610,7 +639,10 @@ static double eval_forces(int64_t n, const double L[3], const double *x,
 {
     double ev[8];
     if (p->potential == OR_POT_LJ) {
-        or_forces_lj(n, L, x, y, z, l->off, l->idx, &p->lj, fx, fy, fz, ev);
+        if (p->threads > 1)
+            or_forces_lj_omp(n, L, x, y, z, l->off, l->idx, &p->lj, fx, fy, fz, ev, p->threads);
+        else
+            or_forces_lj(n, L, x, y, z, l->off, l->idx, &p->lj, fx, fy, fz, ev);
         return ev[1];
     }
     or_forces_eam(n, L, x, y, z, l->off, l->idx, &p->fs, rho, fp, fx, fy, fz, NULL, ev);
@@ -618,9 +650,10 @@ static double eval_forces(int64_t n, const double L[3], const double *x,
 }
 
 static double kinetic(int64_t n, const double *vx, const double *vy,
-                      const double *vz, double mass)
+                      const double *vz, double mass, int32_t threads)
 {
     double s = 0.0;
+#pragma omp parallel for if (threads > 1) num_threads(threads) schedule(static) reduction(+ : s)
     for (int64_t i = 0; i < n; ++i) s += vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
     return 0.5 * mass * s;
 }
@@ -650,12 +683,14 @@ int64_t or_md_run(int64_t n, const double L[3], double *x, double *y,
     memcpy(xr, x, nb); memcpy(yr, y, nb); memcpy(zr, z, nb);
     double ep = eval_forces(n, L, x, y, z, &l, p, fx, fy, fz, rho, fp);
     if (epot) epot[0] = ep;
-    if (ekin) ekin[0] = kinetic(n, vx, vy, vz, p->mass);
+    const int32_t th = p->threads > 1 ? p->threads : 1;
+    if (ekin) ekin[0] = kinetic(n, vx, vy, vz, p->mass, th);
 
     struct timespec t0, t1;
     clock_gettime(CLOCK_MONOTONIC, &t0);
     for (int64_t s = 1; s <= steps; ++s) {
         double maxd2 = 0.0;
+#pragma omp parallel for if (th > 1) num_threads(th) schedule(static) reduction(max : maxd2)
         for (int64_t i = 0; i < n; ++i) {
             vx[i] += hk * fx[i]; vy[i] += hk * fy[i]; vz[i] += hk * fz[i];
             x[i] += p->dt * vx[i]; y[i] += p->dt * vy[i]; z[i] += p->dt * vz[i];
@@ -672,11 +707,12 @@ int64_t or_md_run(int64_t n, const double L[3], double *x, double *y,
             memcpy(xr, x, nb); memcpy(yr, y, nb); memcpy(zr, z, nb);
         }
         ep = eval_forces(n, L, x, y, z, &l, p, fx, fy, fz, rho, fp);
+#pragma omp parallel for if (th > 1) num_threads(th) schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             vx[i] += hk * fx[i]; vy[i] += hk * fy[i]; vz[i] += hk * fz[i];
         }
         if (epot) epot[s] = ep;
-        if (ekin) ekin[s] = kinetic(n, vx, vy, vz, p->mass);
+        if (ekin) ekin[s] = kinetic(n, vx, vy, vz, p->mass, th);
     }
     clock_gettime(CLOCK_MONOTONIC, &t1);
     if (loop_seconds)

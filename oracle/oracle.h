@@ -79,17 +79,27 @@ typedef struct {
     double A, d, c, c0, c1, c2;
 } or_fs_t;
 
-/* Lennard-Jones forces by the pair loop with Newton's third law (Sec. 2.2,
- * pair-force listing): each unordered pair {i,j} with r < rc is visited once
- * from the lower index, F = -(1/r) dPhi/dr R with R = r_i - r_j is added to
- * f_i and subtracted from f_j.  The list may be any superset of the pairs
- * within rc (a full list; only entries j > i are used).
+/* Lennard-Jones forces as the gradient of the pair energy (the pair force
+ * of Sec. 2.2): with U = 1/2 sum_i sum_{j != i, r_ij < rc} Phi(r_ij),
+ *   F_i = -dU/dr_i = sum_{j in N(i), r_ij < rc} -(1/r) dPhi/dr (r_i - r_j),
+ * summed over atom i's own row of a full list (every j != i within the
+ * list cutoff, each pair in both rows; any superset of the pairs within rc).
  * ev[8] receives: E (truncated), E_shift (each pair shifted by -Phi(rc)),
- * virial W_xx, W_yy, W_zz, W_xy, W_xz, W_yz (sum over pairs of f_s R_a R_b). */
+ * virial W_xx, W_yy, W_zz, W_xy, W_xz, W_yz (sum over pairs of f_s R_a R_b),
+ * each pair's share taken half from each of its two rows. */
 void or_forces_lj(int64_t n, const double L[3], const double *x,
                   const double *y, const double *z, const int64_t *offsets,
                   const int32_t *idx, const or_lj_t *p, double *fx,
                   double *fy, double *fz, double ev[8]);
+
+/* The same computation with the rows shared among `threads` OpenMP threads
+ * (each force written by the thread of its row: no races); forces are the
+ * same bits as or_forces_lj, the energy and virial sums differ only in the
+ * order of their terms.  For timing the oracle on all cores. */
+void or_forces_lj_omp(int64_t n, const double L[3], const double *x,
+                      const double *y, const double *z, const int64_t *offsets,
+                      const int32_t *idx, const or_lj_t *p, double *fx,
+                      double *fy, double *fz, double ev[8], int32_t threads);
 
 /* Embedded-atom forces in the three steps of Sec. 3.1 (after Eqs. 1-2):
  * (1) rho_i = sum_j psi(r_ij) by the pair loop, (2) F_i(rho_i) per atom,
@@ -175,6 +185,7 @@ typedef struct {
     double mass;
     double force_to_accel;  /* 1 in reduced units; 1/103.6427 for eV, A, amu, fs */
     int32_t reverse_order;  /* 1: visit each neighbour row in reverse order */
+    int32_t threads;        /* > 1: LJ forces and the per-atom loops on this many OpenMP threads */
 } or_md_params_t;
 
 /* Runs `steps` velocity-Verlet steps in place.  Before the first step the

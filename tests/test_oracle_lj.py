@@ -154,3 +154,20 @@ def test_lj_cutoff_is_strict_and_list_superset_ok(orc):
     off2, idx2 = orc.neighbors_brute(x, L, 5.0)
     f2, ev2 = orc.forces_lj(x, L, off2, idx2, rc=2.5)
     assert np.array_equal(f, f2) and np.array_equal(ev, ev2)
+
+
+def test_lj_openmp_rows_match_the_serial_oracle(orc):
+    """The all-core timing variant computes the same rows: forces bit for
+    bit, energy and virial to the rounding of a different summation order."""
+    s = inputs.jitter(inputs.lj_fcc(ncell=7), 0.08, seed=31)
+    x = orc.wrap(s.x, s.L)
+    off, idx = orc.neighbors_cells(x, s.L, 2.8)
+    f1, e1 = orc.forces_lj(x, s.L, off, idx)
+    f4, e4 = orc.forces_lj_omp(x, s.L, off, idx, threads=4)
+    assert np.array_equal(f1, f4)
+    assert np.allclose(e4, e1, rtol=1e-12, atol=1e-10)
+    # and a short all-core run follows the single-thread trajectory
+    a = orc.md_run(s.x.copy(), s.v.copy(), s.L, 10, r_list=2.8, skin=0.3, dt=0.005)
+    b = orc.md_run(s.x.copy(), s.v.copy(), s.L, 10, r_list=2.8, skin=0.3, dt=0.005, threads=4)
+    assert np.array_equal(a["x"], b["x"]) and a["builds"] == b["builds"]
+    assert np.allclose(a["epot"], b["epot"], rtol=1e-12)
