@@ -350,12 +350,27 @@ int md_forces_tab(const md_box_t *box, int64_t n, uint32_t *xs,
 #define MD_MLP_HID    64
 #define MD_MLP_NPARAM 5313
 
+/* Activation form of the network's matrix products (md_mlp_t.activations):
+ *   MD_MLP_ACT_BF16  every vector entering a product is rounded to bfloat16
+ *                    (the form above; the default);
+ *   MD_MLP_ACT_FP32  every such vector is split exactly into three bfloat16
+ *                    terms (hi + mid + lo, together the FP32 significand) and
+ *                    the products of the three are summed on the matrix
+ *                    cores in FP32: the network with FP32 activations and
+ *                    the same bfloat16 parameters (three times the matrix
+ *                    work).  Training (md_mlp_grad, md_mlp_train_step) always
+ *                    uses the BF16 form. */
+#define MD_MLP_ACT_BF16 0
+#define MD_MLP_ACT_FP32 1
+
 typedef struct md_mlp {
     double rc;                  /* descriptor cutoff */
     double mu0, dmu;            /* Gaussian centres mu_k = mu0 + k dmu */
     double width;               /* Gaussian width w */
     float mean[MD_MLP_IN];      /* input normalisation */
     float inv_std[MD_MLP_IN];
+    int32_t activations;        /* MD_MLP_ACT_BF16 or MD_MLP_ACT_FP32 */
+    int32_t reserved;           /* 0 */
 } md_mlp_t;
 
 /* Longest list row (row_cap) the descriptor passes accept: the in-range
@@ -672,6 +687,23 @@ typedef struct md_system {
  * bracketed by HIP events on `stream` and their elapsed times are added to
  * force_ms / force_calls. */
 int md_run(md_system_t *sys, int64_t steps, void *stream);
+
+/* ---- measurement aid ----
+ *
+ * The achievable peaks of this GPU are measured, not assumed: md_probe runs
+ * `blocks` blocks of 256 threads, each thread `iters` iterations of one kind
+ * of arithmetic on independent chains, and writes nothing the caller needs
+ * (out: a device word of the kind's type, written only in an impossible
+ * case).  Time it with events on `stream`; work per launch:
+ *   MD_PROBE_FMA_F32:   blocks * 256 * iters * 8 FP32 fused multiply-adds
+ *   MD_PROBE_FMA_F64:   blocks * 256 * iters * 8 FP64 fused multiply-adds
+ *   MD_PROBE_MFMA_BF16: blocks * 4 * iters * 4 v_mfma_f32_16x16x32_bf16
+ *                       (16,384 operations each). */
+#define MD_PROBE_FMA_F32   0
+#define MD_PROBE_FMA_F64   1
+#define MD_PROBE_MFMA_BF16 2
+
+int md_probe(int32_t kind, int64_t iters, int32_t blocks, void *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -57,14 +57,14 @@ int ws_check_n(int64_t n, void *ws, size_t bytes, WsLayout &w)
 }
 
 // descriptor geometry: positive width and spacing, 0 < rc, finite
-// normalisation
+// normalisation, a known activation form
 bool mlp_ok(const md_mlp_t *m)
 {
     if (!m || !(m->rc > 0.0) || !(m->width > 0.0) || !(m->dmu > 0.0) || !std::isfinite(m->mu0)) return false;
     if (!std::isfinite(m->rc) || !std::isfinite(m->width) || !std::isfinite(m->dmu)) return false;
     for (int k = 0; k < MD_MLP_IN; ++k)
         if (!std::isfinite(m->mean[k]) || !std::isfinite(m->inv_std[k])) return false;
-    return true;
+    return m->activations == MD_MLP_ACT_BF16 || m->activations == MD_MLP_ACT_FP32;
 }
 
 uint64_t spread3(uint64_t v)

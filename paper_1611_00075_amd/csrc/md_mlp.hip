@@ -79,6 +79,58 @@ __device__ __forceinline__ bf16x8 pack8(const float (&u)[8])
     return __builtin_convertvector(v, bf16x8);
 }
 
+// v rounded to bfloat16 (nearest even), as a float: the value pack() stores.
+__device__ __forceinline__ float bf16_round(float v)
+{
+    uint32_t u = __float_as_uint(v);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+// A matrix-core B operand of NS bfloat16 terms whose sum is the FP32 vector
+// it was made from: NS = 1 rounds the activations to bfloat16 (the BF16
+// form); NS = 3 splits each value exactly into hi + mid + lo terms (each
+// residual is exact in FP32, and 3 x 8 significant bits carry the FP32
+// significand), so the product of bfloat16 weights and the split operand,
+// accumulated in FP32, is the product with FP32 activations (the
+// FP32-activation form).
+template <int NS>
+struct Opd {
+    bf16x8 p[NS];
+};
+
+template <int NS>
+__device__ __forceinline__ Opd<NS> split8(const float (&u)[8])
+{
+    Opd<NS> o;
+    float r[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = u[j];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        o.p[k] = pack8(r);
+        if (k + 1 < NS)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) r[j] -= bf16_round(r[j]);
+    }
+    return o;
+}
+
+template <int NS>
+__device__ __forceinline__ Opd<NS> split(const f32x4 &lo, const f32x4 &hi)
+{
+    const float u[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    return split8<NS>(u);
+}
+
+template <int NS>
+__device__ __forceinline__ f32x4 mfma_s(const bf16x8 &a, const Opd<NS> &b, f32x4 c)
+{
+#pragma unroll
+    for (int k = 0; k < NS; ++k) c = mfma(a, b.p[k], c);
+    return c;
+}
+
 __device__ __forceinline__ float sigm(float a)
 {
     return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-a * kLog2e));
@@ -209,10 +261,11 @@ __device__ __forceinline__ bf16x8 op(const WeightsLds &L, int o, int lane)
 
 // ---- the network on one tile of 16 atoms (one wavefront) --------------------
 
+template <int NS>
 struct Fwd {
     f32x4 ds1[4], ds2[4];   // silu'(a1), silu'(a2) of lane's atom, features 16t + 4g + r
     f32x4 h[4], h2[4];      // silu(a1) before rounding, silu(a2)
-    bf16x8 h1[2];           // layer-2 B operand
+    Opd<NS> h1[2];          // layer-2 B operand
     float E;                // energy of atom lane % 16
 };
 
@@ -223,13 +276,14 @@ __device__ __forceinline__ float2 silu2(float a)
     return make_float2(a * s, s * __builtin_fmaf(a, 1.f - s, 1.f));
 }
 
-__device__ __forceinline__ void forward(const WeightsLds &L, int lane, const bf16x8 &X, Fwd &F)
+template <int NS>
+__device__ __forceinline__ void forward(const WeightsLds &L, int lane, const Opd<NS> &X, Fwd<NS> &F)
 {
     const int g = lane >> 4;
     const f32x4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const f32x4 a = mfma(op(L, kOpL1 + t, lane), X, z);
+        const f32x4 a = mfma_s<NS>(op(L, kOpL1 + t, lane), X, z);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float2 v = silu2(a[r] + L.b1[16 * t + 4 * g + r]);
@@ -237,13 +291,13 @@ __device__ __forceinline__ void forward(const WeightsLds &L, int lane, const bf1
             F.ds1[t][r] = v.y;
         }
     }
-    F.h1[0] = pack(F.h[0], F.h[1]);
-    F.h1[1] = pack(F.h[2], F.h[3]);
+    F.h1[0] = split<NS>(F.h[0], F.h[1]);
+    F.h1[1] = split<NS>(F.h[2], F.h[3]);
     float e = 0.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        f32x4 a = mfma(op(L, kOpL2 + 2 * t, lane), F.h1[0], z);
-        a = mfma(op(L, kOpL2 + 2 * t + 1, lane), F.h1[1], a);
+        f32x4 a = mfma_s<NS>(op(L, kOpL2 + 2 * t, lane), F.h1[0], z);
+        a = mfma_s<NS>(op(L, kOpL2 + 2 * t + 1, lane), F.h1[1], a);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int f = 16 * t + 4 * g + r;
@@ -259,7 +313,8 @@ __device__ __forceinline__ void forward(const WeightsLds &L, int lane, const bf1
 }
 
 // dE/dx for the tile: lane's atom, input features 4g + r
-__device__ __forceinline__ f32x4 backward_input(const WeightsLds &L, int lane, const Fwd &F)
+template <int NS>
+__device__ __forceinline__ f32x4 backward_input(const WeightsLds &L, int lane, const Fwd<NS> &F)
 {
     const int g = lane >> 4;
     const f32x4 z = {0.f, 0.f, 0.f, 0.f};
@@ -268,17 +323,17 @@ __device__ __forceinline__ f32x4 backward_input(const WeightsLds &L, int lane, c
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) d[t][r] = L.w3[16 * t + 4 * g + r] * F.ds2[t][r];
-    const bf16x8 D2[2] = {pack(d[0], d[1]), pack(d[2], d[3])};
+    const Opd<NS> D2[2] = {split<NS>(d[0], d[1]), split<NS>(d[2], d[3])};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        f32x4 p = mfma(op(L, kOpB2 + 2 * t, lane), D2[0], z);
-        p = mfma(op(L, kOpB2 + 2 * t + 1, lane), D2[1], p);
+        f32x4 p = mfma_s<NS>(op(L, kOpB2 + 2 * t, lane), D2[0], z);
+        p = mfma_s<NS>(op(L, kOpB2 + 2 * t + 1, lane), D2[1], p);
 #pragma unroll
         for (int r = 0; r < 4; ++r) d[t][r] = p[r] * F.ds1[t][r];
     }
-    const bf16x8 D1[2] = {pack(d[0], d[1]), pack(d[2], d[3])};
-    f32x4 dx = mfma(op(L, kOpB1, lane), D1[0], z);
-    return mfma(op(L, kOpB1 + 1, lane), D1[1], dx);
+    const Opd<NS> D1[2] = {split<NS>(d[0], d[1]), split<NS>(d[2], d[3])};
+    f32x4 dx = mfma_s<NS>(op(L, kOpB1, lane), D1[0], z);
+    return mfma_s<NS>(op(L, kOpB1 + 1, lane), D1[1], dx);
 }
 
 // ---- pass 1 / descriptors / network ---------------------------------------
@@ -390,6 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_desc(int64_t n, MlpArgs p, const
 // Energies E_i (e_atom, may be NULL; FP64 block partial in part if not NULL)
 // and dE/dG (dEdG, may be NULL).  Gin and dEdG may be the same buffer: a
 // wavefront reads its 16 rows before it writes them.
+template <int NS>
 __global__ __launch_bounds__(kBlock) void k_mlp_net(int64_t n, MlpArgs p, const float *Gin,
                                                     const uint16_t *__restrict__ w, float *__restrict__ e_atom,
                                                     float *dEdG, double *__restrict__ part)
@@ -408,24 +464,23 @@ __global__ __launch_bounds__(kBlock) void k_mlp_net(int64_t n, MlpArgs p, const 
 
     for (int64_t c = c0; c < c1; ++c) {
         const int64_t i = c * kChunk + int64_t(wave) * kTile + m;
-        bf16x8 X = {};
+        float u[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (g < 2 && i < n) {
             const float4 u0 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g);
             const float4 u1 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g + 4);
             const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-            float u[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) u[j] = (v[j] - L.mean[8 * g + j]) * L.inv_std[8 * g + j];
-            X = pack8(u);
         }
-        Fwd F;
-        forward(L, lane, X, F);
+        const Opd<NS> X = split8<NS>(u);
+        Fwd<NS> F;
+        forward<NS>(L, lane, X, F);
         if (g == 0 && i < n) {
             if (e_atom) e_atom[i] = F.E;
             esum += double(F.E);
         }
         if (dEdG) {
-            const f32x4 dx = backward_input(L, lane, F);
+            const f32x4 dx = backward_input<NS>(L, lane, F);
             if (i < n) {
                 float4 o;
                 o.x = dx[0] * L.inv_std[4 * g + 0];
@@ -605,8 +660,8 @@ __global__ __launch_bounds__(kBlock) void k_mlp_grad(int64_t batch, const int32_
 #pragma unroll
                 for (int j = 0; j < 8; ++j) T.xT[8 * g + j][h * kTile + m] = f_to_bf16(u[j]);
             }
-            Fwd F;
-            forward(L, lane, X, F);
+            Fwd<1> F;
+            forward<1>(L, lane, Opd<1>{{X}}, F);
             const float err = valid ? F.E - target[row] : 0.f;
             const float gE = scale * err;
             if (g == 0) {
@@ -815,7 +870,10 @@ int mlp_eval(int64_t n, const float *G, const md_mlp_t *mlp, const uint16_t *w, 
 {
     if (n == 0) return MD_OK;
     const MlpArgs a = make_args(nullptr, mlp);
-    hipLaunchKernelGGL(k_mlp_net, dim3(atom_grid(n)), dim3(kBlock), 0, s, n, a, G, w, e_atom, dEdG, nullptr);
+    if (mlp->activations == MD_MLP_ACT_FP32)
+        hipLaunchKernelGGL(k_mlp_net<3>, dim3(atom_grid(n)), dim3(kBlock), 0, s, n, a, G, w, e_atom, dEdG, nullptr);
+    else
+        hipLaunchKernelGGL(k_mlp_net<1>, dim3(atom_grid(n)), dim3(kBlock), 0, s, n, a, G, w, e_atom, dEdG, nullptr);
     MD_HIP_TRY(hipGetLastError());
     return MD_OK;
 }
@@ -842,8 +900,12 @@ int forces_mlp(const md_box_t *box, int64_t n, const uint32_t *xs, int32_t cap, 
             // pass 1b: the network overwrites each row with dE/dG in place
             hipLaunchKernelGGL(k_mlp_desc, dim3(g2), dim3(kBlock), seg_bytes(cap), s, n, a, q, cap, idx, count,
                                dEdG, idx_in, cnt_in);
-            hipLaunchKernelGGL(k_mlp_net, dim3(g1), dim3(kBlock), 0, s, n, a, dEdG, w, e_atom, dEdG,
-                               energy ? part1 : nullptr);
+            if (mlp->activations == MD_MLP_ACT_FP32)
+                hipLaunchKernelGGL(k_mlp_net<3>, dim3(g1), dim3(kBlock), 0, s, n, a, dEdG, w, e_atom, dEdG,
+                                   energy ? part1 : nullptr);
+            else
+                hipLaunchKernelGGL(k_mlp_net<1>, dim3(g1), dim3(kBlock), 0, s, n, a, dEdG, w, e_atom, dEdG,
+                                   energy ? part1 : nullptr);
         }
         const float4 *d4 = reinterpret_cast<const float4 *>(dEdG);
         // pass 2 walks the compact list of pairs within rc (the full list when

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libmd.so")
 MD_OK, MD_ERR_ARG, MD_ERR_BOX, MD_ERR_CAPACITY = 0, -1, -2, -3
 MD_ERR_NONFINITE, MD_ERR_HIP, MD_ERR_WORKSPACE = -4, -5, -6
 MD_NOALLOC_MAX_ATOMS = 1 << 22
+MD_PROBE_FMA_F32, MD_PROBE_FMA_F64, MD_PROBE_MFMA_BF16 = 0, 1, 2
+MD_MLP_ACT_BF16, MD_MLP_ACT_FP32 = 0, 1
 MD_ENERGY, MD_PAIR_FP64, MD_NO_COMPENSATE, MD_MLP_REUSE, MD_XS_ELEMENT = 0x1, 0x2, 0x4, 0x8, 0x10
 MD_KICK_DRIFT, MD_KICK = 1, 2
 MD_SLICE = 8
@@ -81,7 +83,8 @@ MD_MLP_IN, MD_MLP_HID, MD_MLP_NPARAM = 16, 64, 5313
 class MLP(C.Structure):
     """md_mlp_t: descriptor geometry and input normalisation."""
     _fields_ = [("rc", C.c_double), ("mu0", C.c_double), ("dmu", C.c_double), ("width", C.c_double),
-                ("mean", C.c_float * MD_MLP_IN), ("inv_std", C.c_float * MD_MLP_IN)]
+                ("mean", C.c_float * MD_MLP_IN), ("inv_std", C.c_float * MD_MLP_IN),
+                ("activations", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Adam(C.Structure):
@@ -89,10 +92,11 @@ class Adam(C.Structure):
                 ("step", C.c_int64)]
 
 
-def mlp_spec(rc=5.0, mu0=2.0, dmu=0.2, width=0.2, mean=None, inv_std=None) -> MLP:
+def mlp_spec(rc=5.0, mu0=2.0, dmu=0.2, width=0.2, mean=None, inv_std=None, activations=MD_MLP_ACT_BF16) -> MLP:
     m = MLP(float(rc), float(mu0), float(dmu), float(width))
     m.mean[:] = [float(v) for v in (np.zeros(MD_MLP_IN) if mean is None else mean)]
     m.inv_std[:] = [float(v) for v in (np.ones(MD_MLP_IN) if inv_std is None else inv_std)]
+    m.activations = int(activations)
     return m
 
 
@@ -171,6 +175,7 @@ def lib():
                                          C.POINTER(C.c_int32), _vp, C.c_size_t, _vp]
         L.md_forces_lj.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, C.c_int32, _vp, _vp, C.POINTER(LJ),
                                    _vp, _vp, C.c_int32, _vp, C.c_size_t, _vp]
+        L.md_probe.argtypes = [C.c_int32, C.c_int64, C.c_int32, _vp, _vp]
         L.md_forces_lj_noalloc.argtypes = [C.POINTER(Box), C.c_int64, _vp, _vp, C.c_int32, _vp, _vp,
                                            C.POINTER(LJ), _vp, _vp, C.c_int32, _vp]
         L.md_forces_eam.argtypes = [C.POINTER(Box), C.c_int64, _vp, C.c_int32, _vp, _vp, C.POINTER(FS), _vp,
@@ -335,6 +340,11 @@ def md_forces_lj(L, n: int, x, xs, row_cap: int, idx, count, lj: tuple, f, ev, f
                               _ptr(idx, torch.int32, ell_size(n, row_cap), "idx"), _ptr(count, torch.int32, n, "count"),
                               C.byref(p), _ptr(f, fdt, 3 * n, "f"), _ptr(ev, torch.float64, 8, "ev"), int(flags),
                               _ptr(ws, name="ws"), ws.numel(), _stream(stream)), "md_forces_lj")
+
+
+def md_probe(kind: int, iters: int, blocks: int, out, stream=None):
+    """Launch one peak-measurement kernel (see md.h)."""
+    _check(lib().md_probe(int(kind), int(iters), int(blocks), _ptr(out, name="out"), _stream(stream)), "md_probe")
 
 
 def md_forces_lj_noalloc(L, n: int, x, xs, row_cap: int, idx, count, lj: tuple, f, ev, flags: int,

@@ -66,8 +66,11 @@ def init_params(seed: int, e_mean: float = 0.0, w3_scale: float = 0.01) -> np.nd
     return p
 
 
-def spec(mean=None, inv_std=None) -> M.MLP:
-    return M.mlp_spec(RC, MU0, DMU, WIDTH, mean, inv_std)
+def spec(mean=None, inv_std=None, fp32_activations=False) -> M.MLP:
+    """Descriptor geometry and normalisation; fp32_activations selects the
+    network's FP32-activation form (otherwise BF16 activations)."""
+    return M.mlp_spec(RC, MU0, DMU, WIDTH, mean, inv_std,
+                      M.MD_MLP_ACT_FP32 if fp32_activations else M.MD_MLP_ACT_BF16)
 
 
 def normalisation(G: torch.Tensor, tws=None):

@@ -336,3 +336,60 @@ def test_training_abi_rejects_bad_arguments(M):
     with pytest.raises(M.MDError) as ex:
         M.md_mlp_grad(64, None, G, e, sp, w, g, None, tws)
     assert ex.value.code == M.MD_ERR_WORKSPACE
+
+
+# ------------------------------------------------------------------ FP32-activation form
+def test_network_fp32_activations_vs_oracle(M, orc, om):
+    """The FP32-activation form (each activation split exactly into three
+    bfloat16 terms on the matrix cores) against the oracle's FP64 network
+    with the same bfloat16 parameters: every atom within FP32 rounding, far
+    inside the BF16 rounding effect."""
+    from paper_1611_00075_amd import mlp as P
+    x, L = _system(5, 7)
+    x = orc.wrap(x, L)
+    off, idx = orc.neighbors_brute(x, L, 6.0)
+    G32 = om.descriptors(x, L, off, idx, om.Spec()).astype(np.float32)
+    n = len(G32)
+    sp = P.spec(np.zeros(16), np.full(16, 0.25), fp32_activations=True)
+    osp = om.Spec(mean=np.zeros(16), inv_std=np.full(16, 0.25))
+    p, bits = _params(om, 7)
+    e = torch.zeros(n, dtype=torch.float32, device="cuda")
+    d = torch.zeros((n, 16), dtype=torch.float32, device="cuda")
+    M.md_mlp_eval(n, torch.tensor(G32, device="cuda"), sp, bits.cuda(), e, d)
+    eg, dg = e.cpu().numpy().astype(np.float64), d.cpu().numpy().astype(np.float64)
+    e64, d64 = om.energy(G32.astype(np.float64), osp, p, bf16=False)
+    e16, d16 = om.energy(G32.astype(np.float64), osp, p, bf16=True)
+    de = np.abs(eg - e64) / (1.0 + np.abs(e64))
+    dd = np.abs(dg - d64).max(axis=1) / (np.abs(d64).max(axis=1) + 1e-3)
+    print(f"FP32-activation network: energy <= {de.max():.2e}, dE/dG <= {dd.max():.2e} "
+          f"(BF16 effect {np.abs(e16 - e64).max():.2e}, {np.abs(d16 - d64).max():.2e})")
+    assert de.max() < 2e-6 and dd.max() < 2e-5
+    assert np.abs(eg - e64).max() < 0.02 * np.abs(e16 - e64).max()
+
+
+def test_forces_fp32_activations_vs_oracle(M, orc, om):
+    """Full forces of the FP32-activation form against the oracle's FP64
+    forces (FP64 network, same bfloat16 parameters): FP32 accuracy, a small
+    fraction of the BF16 effect."""
+    from paper_1611_00075_amd import mlp as P
+    x, L = _system(10, 6, drop=5, sigma=0.15)
+    x = orc.wrap(x, L)
+    off, idx = orc.neighbors_brute(x, L, 6.0)
+    G = om.descriptors(x, L, off, idx, om.Spec())
+    mean = G.mean(0).astype(np.float32).astype(np.float64)
+    inv = (1.0 / G.std(0)).astype(np.float32).astype(np.float64)
+    osp = om.Spec(mean=mean, inv_std=inv)
+    p, bits = _params(om, 11)
+    _, d16 = om.energy(G, osp, p, bf16=True)
+    e64, d64 = om.energy(G, osp, p, bf16=False)
+    f16, _ = om.forces(x, L, off, idx, osp, d16)
+    f64, _ = om.forces(x, L, off, idx, osp, d64)
+    sim = _mlp_sim(M, x, L, P.spec(mean, inv, fp32_activations=True), bits.cuda())
+    sim.compute_forces(energy=True, site=True)
+    fg = sim.forces()
+    eg = sim.by_id(sim.e_atom).astype(np.float64)
+    err = np.linalg.norm(fg - f64) / np.linalg.norm(f64)
+    effect = np.linalg.norm(f16 - f64) / np.linalg.norm(f64)
+    print(f"MLP FP32-activation forces: |gpu - fp64 oracle| {err:.2e} normwise (BF16 effect {effect:.2e})")
+    assert err < 2e-5 and err < 0.05 * effect
+    assert np.abs(eg - e64).max() < 1e-5 * (1.0 + np.abs(e64).max())
