@@ -697,7 +697,7 @@ int md_run(md_system_t *sys, int64_t steps, void *stream);
  * case).  Time it with events on `stream`; work per launch:
  *   MD_PROBE_FMA_F32:   blocks * 256 * iters * 8 FP32 fused multiply-adds
  *   MD_PROBE_FMA_F64:   blocks * 256 * iters * 8 FP64 fused multiply-adds
- *   MD_PROBE_MFMA_BF16: blocks * 4 * iters * 4 v_mfma_f32_16x16x32_bf16
+ *   MD_PROBE_MFMA_BF16: blocks * 4 * iters * 8 v_mfma_f32_16x16x32_bf16
  *                       (16,384 operations each). */
 #define MD_PROBE_FMA_F32   0
 #define MD_PROBE_FMA_F64   1

@@ -16,6 +16,9 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SOURCES = ["oracle.c", "mlp.c"]
 
 
+COMPILER_FLAGS = "gcc -O2 -std=gnu11 -fPIC -shared -ffp-contract=off -fopenmp -lm"
+
+
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (plain C, FP64, no FMA contraction)."""
     if force or not os.path.exists(_LIB_PATH):
@@ -75,6 +78,9 @@ def _declare(L):
         f.restype = C.c_int64
     L.or_forces_lj.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
                                C.POINTER(LJParams), _dp, _dp, _dp, _dp]
+    L.or_neighbors_cells_omp.argtypes = [C.c_int64, _dp, C.c_double, _dp, _dp, _dp, _i64p, _i32p, C.c_int64,
+                                         C.c_int32]
+    L.or_neighbors_cells_omp.restype = C.c_int64
     L.or_forces_lj_omp.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
                                    C.POINTER(LJParams), _dp, _dp, _dp, _dp, C.c_int32]
     L.or_forces_eam.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _i64p, _i32p,
@@ -146,6 +152,11 @@ def _neighbors(fn, x, L, r_list):
 def neighbors_brute(x, L, r_list):
     """CSR full list {j != i : r^2 < r_list^2}, rows ascending (O(N^2))."""
     return _neighbors(lib().or_neighbors_brute, x, L, r_list)
+
+
+def neighbors_cells_omp(x, L, r_list, threads=2):
+    """neighbors_cells with the rows shared among OpenMP threads (timing aid)."""
+    return _neighbors(lambda *a: lib().or_neighbors_cells_omp(*a, int(threads)), x, L, r_list)
 
 
 def neighbors_cells(x, L, r_list):
