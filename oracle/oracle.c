@@ -175,6 +175,73 @@ int64_t or_neighbors_cells(int64_t n, const double L[3], double r_list,
     return total;
 }
 
+/* The same list with the rows shared among `threads` OpenMP threads: each
+ * row counted, the offsets summed, each row filled and sorted by its own
+ * thread.  The same output as or_neighbors_cells; for timing only. */
+static int64_t cell_row(int64_t i, const int32_t nc[3], const int32_t *cx, const int32_t *cy, const int32_t *cz,
+                        const int64_t *head, const int64_t *next, const double L[3], double rl2, const double *x,
+                        const double *y, const double *z, int32_t *out)
+{
+    int32_t sx[3], sy[3], sz[3];
+    int mx = stencil_axis(cx[i], nc[0], sx);
+    int my = stencil_axis(cy[i], nc[1], sy);
+    int mz = stencil_axis(cz[i], nc[2], sz);
+    double d[3];
+    int64_t m = 0;
+    for (int a = 0; a < mx; ++a)
+        for (int b = 0; b < my; ++b)
+            for (int e = 0; e < mz; ++e) {
+                int64_t c = sx[a] + (int64_t)nc[0] * (sy[b] + (int64_t)nc[1] * sz[e]);
+                for (int64_t j = head[c]; j >= 0; j = next[j]) {
+                    if (j == i) continue;
+                    if (dist2(L, x, y, z, i, j, d) < rl2) {
+                        if (out) out[m] = (int32_t)j;
+                        ++m;
+                    }
+                }
+            }
+    if (out) qsort(out, (size_t)m, sizeof(int32_t), cmp_i32);
+    return m;
+}
+
+int64_t or_neighbors_cells_omp(int64_t n, const double L[3], double r_list,
+                               const double *x, const double *y, const double *z,
+                               int64_t *offsets, int32_t *idx, int64_t cap, int32_t threads)
+{
+    int32_t nc[3];
+    for (int a = 0; a < 3; ++a) {
+        nc[a] = (int32_t)floor(L[a] / r_list);
+        if (nc[a] < 1) nc[a] = 1;
+    }
+    const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    int32_t *cx = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *cy = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *cz = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *head = malloc(sizeof(int64_t) * (size_t)ncell);
+    int64_t *next = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    or_cell_coords(n, L, nc, x, y, z, cx, cy, cz);
+    for (int64_t c = 0; c < ncell; ++c) head[c] = -1;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        int64_t c = cx[i] + (int64_t)nc[0] * (cy[i] + (int64_t)nc[1] * cz[i]);
+        next[i] = head[c];
+        head[c] = i;
+    }
+    const double rl2 = r_list * r_list;
+    offsets[0] = 0;
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i)
+        offsets[i + 1] = cell_row(i, nc, cx, cy, cz, head, next, L, rl2, x, y, z, NULL);
+    for (int64_t i = 0; i < n; ++i) offsets[i + 1] += offsets[i];
+    const int64_t total = offsets[n];
+    if (total <= cap) {
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i)
+            cell_row(i, nc, cx, cy, cz, head, next, L, rl2, x, y, z, idx + offsets[i]);
+    }
+    free(cx); free(cy); free(cz); free(head); free(next);
+    return total;
+}
+
 /* ------------------------------------------------------------------ */
 /* Lennard-Jones: forces as the gradient of the pair energy            */
 /* ------------------------------------------------------------------ */
@@ -606,17 +673,24 @@ typedef struct {
     int64_t cap;
 } list_t;
 
+static int64_t cells_list(int64_t n, const double L[3], double r_list, const double *x, const double *y,
+                          const double *z, list_t *l, int32_t threads)
+{
+    if (threads > 1) return or_neighbors_cells_omp(n, L, r_list, x, y, z, l->off, l->idx, l->cap, threads);
+    return or_neighbors_cells(n, L, r_list, x, y, z, l->off, l->idx, l->cap);
+}
+
 static int build_list(int64_t n, const double L[3], double r_list,
                       const double *x, const double *y, const double *z,
-                      list_t *l, int reverse)
+                      list_t *l, int reverse, int32_t threads)
 {
-    int64_t need = or_neighbors_cells(n, L, r_list, x, y, z, l->off, l->idx, l->cap);
+    int64_t need = cells_list(n, L, r_list, x, y, z, l, threads);
     if (need > l->cap) {
         free(l->idx);
         l->cap = need + need / 4 + 16;
         l->idx = malloc(sizeof(int32_t) * (size_t)l->cap);
         if (!l->idx) return -1;
-        or_neighbors_cells(n, L, r_list, x, y, z, l->off, l->idx, l->cap);
+        cells_list(n, L, r_list, x, y, z, l, threads);
     }
     if (reverse) {
         for (int64_t i = 0; i < n; ++i) {
@@ -678,7 +752,7 @@ int64_t or_md_run(int64_t n, const double L[3], double *x, double *y,
     const double hk = 0.5 * p->dt * p->force_to_accel / p->mass;
 
     or_wrap(n, L, x, y, z);
-    if (build_list(n, L, p->r_list, x, y, z, &l, p->reverse_order)) goto out;
+    if (build_list(n, L, p->r_list, x, y, z, &l, p->reverse_order, p->threads)) goto out;
     builds = 1;
     memcpy(xr, x, nb); memcpy(yr, y, nb); memcpy(zr, z, nb);
     double ep = eval_forces(n, L, x, y, z, &l, p, fx, fy, fz, rho, fp);
@@ -702,7 +776,7 @@ int64_t or_md_run(int64_t n, const double L[3], double *x, double *y,
         }
         if (maxd2 > half_skin2) {
             or_wrap(n, L, x, y, z);
-            if (build_list(n, L, p->r_list, x, y, z, &l, p->reverse_order)) { builds = -1; goto out; }
+            if (build_list(n, L, p->r_list, x, y, z, &l, p->reverse_order, p->threads)) { builds = -1; goto out; }
             ++builds;
             memcpy(xr, x, nb); memcpy(yr, y, nb); memcpy(zr, z, nb);
         }

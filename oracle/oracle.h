@@ -79,6 +79,13 @@ typedef struct {
     double A, d, c, c0, c1, c2;
 } or_fs_t;
 
+/* or_neighbors_cells with the rows shared among `threads` OpenMP threads
+ * (counted, summed, then filled and sorted row by row): the same output;
+ * for timing the oracle on all cores. */
+int64_t or_neighbors_cells_omp(int64_t n, const double L[3], double r_list,
+                               const double *x, const double *y, const double *z,
+                               int64_t *offsets, int32_t *idx, int64_t cap, int32_t threads);
+
 /* Lennard-Jones forces as the gradient of the pair energy (the pair force
  * of Sec. 2.2): with U = 1/2 sum_i sum_{j != i, r_ij < rc} Phi(r_ij),
  *   F_i = -dU/dr_i = sum_{j in N(i), r_ij < rc} -(1/r) dPhi/dr (r_i - r_j),

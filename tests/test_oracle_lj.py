@@ -171,3 +171,12 @@ def test_lj_openmp_rows_match_the_serial_oracle(orc):
     b = orc.md_run(s.x.copy(), s.v.copy(), s.L, 10, r_list=2.8, skin=0.3, dt=0.005, threads=4)
     assert np.array_equal(a["x"], b["x"]) and a["builds"] == b["builds"]
     assert np.allclose(a["epot"], b["epot"], rtol=1e-12)
+
+
+def test_openmp_cell_list_matches_the_serial_oracle(orc):
+    """The all-core list build gives the serial oracle's rows exactly."""
+    L = np.array([13.0, 11.0, 12.0])
+    x = orc.wrap(inputs.random_gas(2500, L, seed=32), L)
+    o1, i1 = orc.neighbors_cells(x, L, 2.8)
+    o4, i4 = orc.neighbors_cells_omp(x, L, 2.8, threads=4)
+    assert np.array_equal(o1, o4) and np.array_equal(i1, i4)
