@@ -520,17 +520,17 @@ __device__ __forceinline__ int32_t nb_cell(NbWaveLds &L, int64_t n, const double
     return longest;
 }
 
-// One wavefront per cell (Morton rank), several independent wavefronts per
-// block, no block-wide barriers.  The atoms of the up to 27 (125)
-// neighbouring cells are contiguous runs of the sorted arrays; the wave
-// streams them, keeps those within reach of its homes' bounding box, and
-// tests each home atom against 64 kept candidates at a time, compacting hits
-// with a ballot straight into the sliced-ELL rows (entry e of atom i at
-// idx[(i/8 * row_cap/8 + e/8) * 64 + (i%8) * 8 + e%8]).  Row order: stencil
-// cell, then sorted index.  Rows longer than row_cap are counted but
-// truncated (the row is written through a buffer whose range ends at entry
-// row_cap, so stores past it are dropped); the longest row length is folded
-// into *max_count.
+// One wavefront per cell (Morton rank) in one-wave blocks, no block-wide
+// barriers.  The atoms of the up to 27 (125) neighbouring cells are
+// contiguous runs of the sorted arrays; the wave streams them, keeps those
+// within reach of its homes' bounding box, and tests each home atom against
+// 64 kept candidates at a time, compacting hits with a ballot straight into
+// the sliced-ELL rows (entry e of atom i at
+// idx[(i/8 * row_cap/8 + e/8) * 64 + (i%8) * 8 + e%8]).  The stencil's cells
+// are visited in rank order, so each row is sorted by neighbour index.  Rows
+// longer than row_cap are counted but truncated (the row is written through
+// a buffer whose range ends at entry row_cap, so stores past it are
+// dropped); the longest row length is folded into *max_count.
 //
 // Interior cells (no stencil cell wraps around the box and nc >= 2 reach + 2
 // on every axis) use the plain difference x_j - x_i: every candidate is then
@@ -568,23 +568,41 @@ __global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double 
     const int my = stencil_axis(c3[1], g.nc[1], g.reach, ay, iy);
     const int mz = stencil_axis(c3[2], g.nc[2], g.reach, az, iz);
     const int m = mx * my * mz;
+    // (1) each stencil cell's rank, range and periodic image; (2) the cells
+    // ordered by rank, so candidates stream in increasing sorted index and
+    // every row comes out sorted (the 8 rows of a slice then hold their
+    // common neighbours at nearby positions, which the force kernels'
+    // gathers share); (3) a shuffle scan forms the range prefix
+    int32_t *const srank = L.stage, *const sst = L.stage + 128, *const slen = L.stage + 256,
+                   *const simg = L.stage + 384;
+    for (int t = lane; t < m; t += kWave) {
+        // t = a + mx (b + my c) for small mx, my: exact reciprocal multiplies
+        const int q1 = (t * ((65536 + mx - 1) / mx)) >> 16;
+        const int a = t - q1 * mx;
+        const int c = (q1 * ((65536 + my - 1) / my)) >> 16;
+        const int b = q1 - c * my;
+        const int64_t l = ax[a] + int64_t(g.nc[0]) * (ay[b] + int64_t(g.nc[1]) * az[c]);
+        const int32_t r = lin2rank[l];
+        const int32_t st = cell_start[r];
+        srank[t] = r;
+        sst[t] = st;
+        slen[t] = cell_start[r + 1] - st;
+        simg[t] = (ix[a] + 1) | ((iy[b] + 1) << 2) | ((iz[c] + 1) << 4);
+    }
+    wave_sync();
+    for (int t = lane; t < m; t += kWave) {
+        const int32_t r = srank[t];
+        int pos = 0;
+        for (int u = 0; u < m; ++u) pos += srank[u] < r;   // ranks are distinct
+        L.rstart[pos] = sst[t];
+        L.rimg[pos] = simg[t];
+        L.rbase[pos + 1] = slen[t];
+    }
+    wave_sync();
     int32_t carry = 0;
     for (int t0 = 0; t0 < m; t0 += kWave) {
         const int t = t0 + lane;
-        int32_t len = 0;
-        if (t < m) {
-            // t = a + mx (b + my c) for small mx, my: exact reciprocal multiplies
-            const int q1 = (t * ((65536 + mx - 1) / mx)) >> 16;
-            const int a = t - q1 * mx;
-            const int c = (q1 * ((65536 + my - 1) / my)) >> 16;
-            const int b = q1 - c * my;
-            const int64_t l = ax[a] + int64_t(g.nc[0]) * (ay[b] + int64_t(g.nc[1]) * az[c]);
-            const int32_t r = lin2rank[l];
-            const int32_t st = cell_start[r];
-            len = cell_start[r + 1] - st;
-            L.rstart[t] = st;
-            L.rimg[t] = (ix[a] + 1) | ((iy[b] + 1) << 2) | ((iz[c] + 1) << 4);
-        }
+        const int32_t len = t < m ? L.rbase[t + 1] : 0;
         int32_t v = len;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
