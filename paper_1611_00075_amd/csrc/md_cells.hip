@@ -317,6 +317,7 @@ constexpr int kNbTile = kNbChunks * kWave;     // candidates per register tile
 constexpr int kNbStage = 2 * kNbTile;          // staged candidates: a tile plus one raw tile's survivors
 constexpr int kNbWaves = 1;                    // wavefronts (cells) per block
 constexpr int kNbMap = 1024;                   // candidates whose stencil cell is tabulated in LDS
+constexpr int kNbCellsPerWave = 1;             // consecutive cells (Morton ranks) per wavefront
 constexpr int kNbBlock = kNbWaves * kWave;
 
 // Per-wave LDS state: the home atoms' positions (read back as broadcasts),
@@ -526,11 +527,11 @@ __device__ __forceinline__ int32_t nb_cell(NbWaveLds &L, int64_t n, const double
 // within reach of its homes' bounding box, and tests each home atom against
 // 64 kept candidates at a time, compacting hits with a ballot straight into
 // the sliced-ELL rows (entry e of atom i at
-// idx[(i/8 * row_cap/8 + e/8) * 64 + (i%8) * 8 + e%8]).  The stencil's cells
-// are visited in rank order, so each row is sorted by neighbour index.  Rows
-// longer than row_cap are counted but truncated (the row is written through
-// a buffer whose range ends at entry row_cap, so stores past it are
-// dropped); the longest row length is folded into *max_count.
+// idx[(i/8 * row_cap/8 + e/8) * 64 + (i%8) * 8 + e%8]).  Row order: stencil
+// cell (x fastest), then sorted index.  Rows longer than row_cap are counted
+// but truncated (the row is written through a buffer whose range ends at
+// entry row_cap, so stores past it are dropped); the longest row length is
+// folded into *max_count.
 //
 // Interior cells (no stencil cell wraps around the box and nc >= 2 reach + 2
 // on every axis) use the plain difference x_j - x_i: every candidate is then
@@ -540,22 +541,17 @@ __device__ __forceinline__ int32_t nb_cell(NbWaveLds &L, int64_t n, const double
 // bounding-box filter runs when no stencil offset was de-duplicated on any
 // axis (nc >= 2 reach + 1): each stencil cell is then one periodic image,
 // the only one that can lie within r_list of a home.
-__global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double *x, GridArgs g, double rl2,
-                                                        double keep2, int64_t n_cells, const int32_t *cell_start,
-                                                        const int32_t *rank_xyz, const int32_t *lin2rank,
-                                                        int32_t row_cap, int32_t *idx, int32_t *count,
-                                                        int32_t *max_count)
+// The rows of the atoms of cell `rank`; returns the cell's longest row.
+__device__ __forceinline__ int32_t nb_one_cell(NbWaveLds &L, int64_t rank, int64_t n, const double *x,
+                                               const GridArgs &g, double rl2, double keep2,
+                                               const int32_t *cell_start, const int32_t *rank_xyz,
+                                               const int32_t *lin2rank, int32_t row_cap, int32_t *idx,
+                                               int32_t *count)
 {
-    __shared__ NbWaveLds lds_all[kNbWaves];
-    const int lane = threadIdx.x % kWave, wave = uni(threadIdx.x / kWave);
-    NbWaveLds &L = lds_all[wave];
-    const int64_t rank = int64_t(xcd_block(blockIdx.x, gridDim.x)) * kNbWaves + wave;
-    if (rank >= n_cells) return;
+    const int lane = threadIdx.x % kWave;
     const int32_t h0 = uni(cell_start[rank]), h1 = uni(cell_start[rank + 1]);
-    if (h0 == h1) return;
+    if (h0 == h1) return 0;
 
-    // stencil cells: lane t takes cells t and t + 64 (x-fastest order), reads
-    // their ranges, and a shuffle scan forms the range prefix
     const int32_t pk = uni(rank_xyz[rank]);   // packed cell coordinates
     const int32_t c3[3] = {pk & 1023, (pk >> 10) & 1023, pk >> 20};
     bool interior = true, nodup = true;
@@ -568,41 +564,25 @@ __global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double 
     const int my = stencil_axis(c3[1], g.nc[1], g.reach, ay, iy);
     const int mz = stencil_axis(c3[2], g.nc[2], g.reach, az, iz);
     const int m = mx * my * mz;
-    // (1) each stencil cell's rank, range and periodic image; (2) the cells
-    // ordered by rank, so candidates stream in increasing sorted index and
-    // every row comes out sorted (the 8 rows of a slice then hold their
-    // common neighbours at nearby positions, which the force kernels'
-    // gathers share); (3) a shuffle scan forms the range prefix
-    int32_t *const srank = L.stage, *const sst = L.stage + 128, *const slen = L.stage + 256,
-                   *const simg = L.stage + 384;
-    for (int t = lane; t < m; t += kWave) {
-        // t = a + mx (b + my c) for small mx, my: exact reciprocal multiplies
-        const int q1 = (t * ((65536 + mx - 1) / mx)) >> 16;
-        const int a = t - q1 * mx;
-        const int c = (q1 * ((65536 + my - 1) / my)) >> 16;
-        const int b = q1 - c * my;
-        const int64_t l = ax[a] + int64_t(g.nc[0]) * (ay[b] + int64_t(g.nc[1]) * az[c]);
-        const int32_t r = lin2rank[l];
-        const int32_t st = cell_start[r];
-        srank[t] = r;
-        sst[t] = st;
-        slen[t] = cell_start[r + 1] - st;
-        simg[t] = (ix[a] + 1) | ((iy[b] + 1) << 2) | ((iz[c] + 1) << 4);
-    }
-    wave_sync();
-    for (int t = lane; t < m; t += kWave) {
-        const int32_t r = srank[t];
-        int pos = 0;
-        for (int u = 0; u < m; ++u) pos += srank[u] < r;   // ranks are distinct
-        L.rstart[pos] = sst[t];
-        L.rimg[pos] = simg[t];
-        L.rbase[pos + 1] = slen[t];
-    }
-    wave_sync();
+    // stencil cells: lane t takes cells t and t + 64 (x-fastest order), reads
+    // their ranges, and a shuffle scan forms the range prefix
     int32_t carry = 0;
     for (int t0 = 0; t0 < m; t0 += kWave) {
         const int t = t0 + lane;
-        const int32_t len = t < m ? L.rbase[t + 1] : 0;
+        int32_t len = 0;
+        if (t < m) {
+            // t = a + mx (b + my c) for small mx, my: exact reciprocal multiplies
+            const int q1 = (t * ((65536 + mx - 1) / mx)) >> 16;
+            const int a = t - q1 * mx;
+            const int c = (q1 * ((65536 + my - 1) / my)) >> 16;
+            const int b = q1 - c * my;
+            const int64_t l = ax[a] + int64_t(g.nc[0]) * (ay[b] + int64_t(g.nc[1]) * az[c]);
+            const int32_t r = lin2rank[l];
+            const int32_t st = cell_start[r];
+            len = cell_start[r + 1] - st;
+            L.rstart[t] = st;
+            L.rimg[t] = (ix[a] + 1) | ((iy[b] + 1) << 2) | ((iz[c] + 1) << 4);
+        }
         int32_t v = len;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
@@ -618,8 +598,26 @@ __global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double 
         for (int t = lane; t < m; t += kWave)
             for (int32_t q = L.rbase[t], e = L.rbase[t + 1]; q < e; ++q) L.cmap[q] = uint8_t(t);
     wave_sync();
-    int32_t longest = interior ? nb_cell<true>(L, n, x, g, rl2, keep2, nodup, h0, h1, m, carry, row_cap, idx, count)
+    return interior ? nb_cell<true>(L, n, x, g, rl2, keep2, nodup, h0, h1, m, carry, row_cap, idx, count)
                                : nb_cell<false>(L, n, x, g, rl2, keep2, nodup, h0, h1, m, carry, row_cap, idx, count);
+}
+
+__global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double *x, GridArgs g, double rl2,
+                                                        double keep2, int64_t n_cells, const int32_t *cell_start,
+                                                        const int32_t *rank_xyz, const int32_t *lin2rank,
+                                                        int32_t row_cap, int32_t *idx, int32_t *count,
+                                                        int32_t *max_count)
+{
+    __shared__ NbWaveLds lds_all[kNbWaves];
+    const int lane = threadIdx.x % kWave, wave = uni(threadIdx.x / kWave);
+    NbWaveLds &L = lds_all[wave];
+    const int64_t first = (int64_t(xcd_block(blockIdx.x, gridDim.x)) * kNbWaves + wave) * kNbCellsPerWave;
+    int32_t longest = 0;
+    for (int c = 0; c < kNbCellsPerWave && first + c < n_cells; ++c) {
+        longest = max(longest, nb_one_cell(L, first + c, n, x, g, rl2, keep2, cell_start, rank_xyz, lin2rank,
+                                           row_cap, idx, count));
+        wave_sync();
+    }
     for (int o = kWave / 2; o > 0; o >>= 1) longest = max(longest, __shfl_xor(longest, o, kWave));
     // *max_count only grows, so a wave whose longest row does not exceed a
     // value already there has nothing to add: the check keeps the atomics on
@@ -644,7 +642,8 @@ int build_neighbors(const md_grid_t *grid, int64_t n, const double *x, const int
     const double keep2 = rl2 * (1.0 + 1e-9);
     int rc = launch_fill_i32(max_count, 1, 0, s);
     if (rc) return rc;
-    const uint32_t nb = uint32_t((grid->n_cells + kNbWaves - 1) / kNbWaves);
+    const int64_t per_block = int64_t(kNbWaves) * kNbCellsPerWave;
+    const uint32_t nb = uint32_t((grid->n_cells + per_block - 1) / per_block);
     if (n > 0) {
         hipLaunchKernelGGL(k_neighbors, dim3(nb), dim3(kNbBlock), 0, s, n, x, g, rl2, keep2, grid->n_cells,
                            cell_start, ws_ptr<int32_t>(ws, w.rank2lin), ws_ptr<int32_t>(ws, w.lin2rank), row_cap, idx,
