@@ -318,6 +318,7 @@ constexpr int kNbStage = 2 * kNbTile;          // staged candidates: a tile plus
 constexpr int kNbWaves = 1;                    // wavefronts (cells) per block
 constexpr int kNbMap = 1024;                   // candidates whose stencil cell is tabulated in LDS
 constexpr int kNbCellsPerWave = 1;             // consecutive cells (Morton ranks) per wavefront
+constexpr uint32_t kNbXcdChunk = 256;          // consecutive blocks (cells) an XCD takes at a time
 constexpr int kNbBlock = kNbWaves * kWave;
 
 // Per-wave LDS state: the home atoms' positions (read back as broadcasts),
@@ -611,7 +612,8 @@ __global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double 
     __shared__ NbWaveLds lds_all[kNbWaves];
     const int lane = threadIdx.x % kWave, wave = uni(threadIdx.x / kWave);
     NbWaveLds &L = lds_all[wave];
-    const int64_t first = (int64_t(xcd_block(blockIdx.x, gridDim.x)) * kNbWaves + wave) * kNbCellsPerWave;
+    const int64_t first = (int64_t(xcd_chunked(blockIdx.x, gridDim.x, kNbXcdChunk)) * kNbWaves + wave) *
+                          kNbCellsPerWave;
     int32_t longest = 0;
     for (int c = 0; c < kNbCellsPerWave && first + c < n_cells; ++c) {
         longest = max(longest, nb_one_cell(L, first + c, n, x, g, rl2, keep2, cell_start, rank_xyz, lin2rank,
