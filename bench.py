@@ -84,16 +84,17 @@ def recorded_pair(k1, k2, field="traffic_bytes"):
 
 
 def valu_frac(key):
-    """Issued VALU instructions per CU per clock of a kernel over the same
-    figure for the FP32 FMA loop (the vector ALU's measured ceiling, same
-    counters and normalisation), or None."""
-    k, p = recorded(key, "valu_inst_per_cu_clk"), recorded("k_probe_fma_f32", "valu_inst_per_cu_clk")
-    return None if k is None or not p else k / p
+    """Fraction of the vector ALU's issue cycles a kernel used: VALU issue
+    events (SQ_INSTS_VALU less the dual-issued second instructions,
+    SQ_ACTIVE_INST_VALU2) over the 4 SIMDs' quad-cycles of the dispatch, so
+    at most 1; or None.  The FP32 FMA loop reaches the value recorded for
+    k_probe_fma_f32 (about 0.88)."""
+    return recorded(key, "valu_issue_frac")
 
 
 def mfma_frac(key):
     """Matrix-core busy cycles of a kernel over the same figure for the BF16
-    matrix-core loop, or None."""
+    matrix-core loop (which reaches the published BF16 rate), or None."""
     k, p = recorded(key, "mfma_busy_per_cu_clk"), recorded("k_probe_mfma", "mfma_busy_per_cu_clk")
     return None if k is None or not p else k / p
 
@@ -174,7 +175,7 @@ def roofline_hbm(kernel, byt, ms, copy_gbs, traffic, valu):
     return {"bound": "hbm", "kernel": kernel, "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": a / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": byt, "launch_ms": ms,
             "copy_GBs": copy_gbs, "frac_of_copy": a / copy_gbs if copy_gbs else None,
-            "valu_frac_of_fma_loop": valu}
+            "valu_issue_frac": valu}
 
 
 def mlp_force_flops(n_atoms, n_in, n_entries):
@@ -510,7 +511,7 @@ def main():
             "list_entries": sim3.n_pairs, "forces_bytes": b3,
             "roofline": roofline_hbm("k_eam_rho + k_eam_force (md_forces_eam)", b3, leg["forces_ms"], copy_gbs,
                                      recorded_pair("k_eam_rho_cu_4M", "k_eam_force_cu_4M"), None),
-            "valu_frac_of_fma_loop": [valu_frac("k_eam_rho_cu_4M"), valu_frac("k_eam_force_cu_4M")],
+            "valu_issue_frac": [valu_frac("k_eam_rho_cu_4M"), valu_frac("k_eam_force_cu_4M")],
             "phases_ms_per_call_api": {k: v[0] for k, v in r3["phases"].items()},
         })
         extra["eam_cu_fcc_100^3"] = leg
@@ -533,7 +534,7 @@ def main():
             "list_entries": sim5.n_pairs, "forces_bytes": b5,
             "roofline": roofline_hbm("k_eam_rho<TB32> + k_eam_force<TB32> (md_forces_tb)", b5, leg["forces_ms"],
                                      copy_gbs, recorded_pair("k_tb_rho_cu_4M", "k_tb_force_cu_4M"), None),
-            "valu_frac_of_fma_loop": [valu_frac("k_tb_rho_cu_4M"), valu_frac("k_tb_force_cu_4M")],
+            "valu_issue_frac": [valu_frac("k_tb_rho_cu_4M"), valu_frac("k_tb_force_cu_4M")],
             "potential": "second-moment tight-binding (exponential psi and Phi, sqrt embedding), "
                          "synthetic Cu-like parameters, rc 5.0 A, list 6.0 A",
         })
@@ -553,7 +554,7 @@ def main():
             "list_entries": sim7.n_pairs, "forces_bytes": b7,
             "roofline": roofline_hbm("k_tab_rho + k_tab_force (md_forces_tab)", b7, leg["forces_ms"], copy_gbs,
                                      recorded_pair("k_tab_rho_cu_4M", "k_tab_force_cu_4M"), None),
-            "valu_frac_of_fma_loop": [valu_frac("k_tab_rho_cu_4M"), valu_frac("k_tab_force_cu_4M")],
+            "valu_issue_frac": [valu_frac("k_tab_rho_cu_4M"), valu_frac("k_tab_force_cu_4M")],
             "potential": "tabulated psi, Phi, F (cubic Hermite between knots) sampled from the FS set: "
                          f"{len(tab7['psi'])} r knots at 0.005 A, {len(tab7['F'])} rho knots; list 5.4 A",
         })
@@ -615,7 +616,7 @@ def main():
                 "roofline": roofline_hbm("k_eam_rho<TBM32> + k_eam_force<TBM32> (md_forces_tbm)", b6,
                                          leg["forces_ms"], copy_gbs,
                                          recorded_pair("k_tbm_rho_cu_au_4M", "k_tbm_force_cu_au_4M"), None),
-                "valu_frac_of_fma_loop": [valu_frac("k_tbm_rho_cu_au_4M"), valu_frac("k_tbm_force_cu_au_4M")],
+                "valu_issue_frac": [valu_frac("k_tbm_rho_cu_au_4M"), valu_frac("k_tbm_force_cu_au_4M")],
             })
             extra[name] = leg
             del sim6, s6
@@ -661,7 +662,7 @@ def main():
             "frac": fl / (t_ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS,
             "frac_of_measured_fma_loop": fl / (t_ms * 1e-3) / 1e12 / peaks["fp32_fma_TFLOPs"],
             "traffic": recorded_traffic("k_mlp_force_cu_4M"),
-            "valu_frac_of_fma_loop": valu_frac("k_mlp_force_cu_4M"),
+            "valu_issue_frac": valu_frac("k_mlp_force_cu_4M"),
             "net_mfma_frac_of_mfma_loop": mfma_frac("k_mlp_net_cu_4M"),
             "launch_ms": t_ms,
         }
@@ -737,55 +738,80 @@ def summarize_counters(dirs):
     per launch (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for
     the benchmark's 2 GiB device copies), issued VALU instructions and
     matrix-core busy cycles per CU per clock (GRBM_GUI_ACTIVE summed over the
-    8 XCDs, so divided by 8 for the dispatch's cycles; 256 CUs).  Launches
+    8 XCDs, so divided by 8 for the dispatch's cycles; 256 CUs), the fraction
+    of VALU issue quad-cycles used (dual-issued pairs counted once), and the
+    texture addressers' busy fraction.  Each directory is one pass; launches
     the device skipped (speculative evaluations) are dropped: their counts
     are far below the kernel's median."""
-    data = _read_counters(dirs)
+    passes = [_read_counters([d]) for d in dirs]
     # copy calibration: the largest copy kernel moves 2 GiB each way
     cal = {"FETCH_SIZE": None, "WRITE_SIZE": None}
-    for (name, grid), ctrs in data.items():
-        if "copyBuffer" in name or "copy_kernel" in name:
-            for c in cal:
-                if c in ctrs:
-                    v = max(ctrs[c])
-                    if cal[c] is None or v > cal[c]:
-                        cal[c] = v
+    for data in passes:
+        for (name, grid), ctrs in data.items():
+            if "copyBuffer" in name or "copy_kernel" in name:
+                for c in cal:
+                    if c in ctrs:
+                        v = max(ctrs[c])
+                        if cal[c] is None or v > cal[c]:
+                            cal[c] = v
     scale = {c: (2 * (1 << 30) / 1024.0) / v if v else None for c, v in cal.items()}
+
+    def kept(vals):
+        vals = np.asarray(vals)
+        med = np.median(vals)
+        return vals[vals >= 0.25 * med] if med > 0 else vals
+
     out = {}
-    for key, (sources, pat, grid) in COUNTER_KERNELS.items():
-        rx = re.compile(pat)
-        hits = [(name, g, ctrs) for (name, g), ctrs in data.items() if rx.search(name) and (grid is None or g == grid)]
-        if not hits:
-            continue
-        name, g, ctrs = max(hits, key=lambda h: max(len(v) for v in h[2].values()))
-        rec = {"kernel": name[:160], "grid_size": g, "sources": sources, "sources_sha256": _sources_sha(sources)}
-
-        def kept(vals):
-            vals = np.asarray(vals)
-            med = np.median(vals)
-            return vals[vals >= 0.25 * med] if med > 0 else vals
-
-        if "FETCH_SIZE" in ctrs and scale["FETCH_SIZE"]:
-            f = kept(ctrs["FETCH_SIZE"])
-            rec.update(fetch_kib=float(f.mean()), fetch_scale=scale["FETCH_SIZE"], launches=int(len(f)))
-        if "WRITE_SIZE" in ctrs and scale["WRITE_SIZE"]:
-            w = kept(ctrs["WRITE_SIZE"])
-            rec.update(write_kib=float(w.mean()), write_scale=scale["WRITE_SIZE"])
-        if "fetch_kib" in rec and "write_kib" in rec:
-            rec["traffic_bytes"] = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] +
-                                             rec["write_kib"] * rec["write_scale"])
-        if "GRBM_GUI_ACTIVE" in ctrs:
+    for data in passes:
+        for key, (sources, pat, grid) in COUNTER_KERNELS.items():
+            rx = re.compile(pat)
+            hits = [(name, g, ctrs) for (name, g), ctrs in data.items()
+                    if rx.search(name) and (grid is None or g == grid)]
+            if not hits:
+                continue
+            name, g, ctrs = max(hits, key=lambda h: max(len(v) for v in h[2].values()))
+            rec = out.setdefault(key, {"kernel": name[:160], "grid_size": g, "sources": sources,
+                                       "sources_sha256": _sources_sha(sources)})
+            if "FETCH_SIZE" in ctrs and scale["FETCH_SIZE"]:
+                f = kept(ctrs["FETCH_SIZE"])
+                rec.update(fetch_kib=float(f.mean()), fetch_scale=scale["FETCH_SIZE"], launches=int(len(f)))
+            if "WRITE_SIZE" in ctrs and scale["WRITE_SIZE"]:
+                w = kept(ctrs["WRITE_SIZE"])
+                rec.update(write_kib=float(w.mean()), write_scale=scale["WRITE_SIZE"])
+            if "GRBM_GUI_ACTIVE" not in ctrs:
+                continue
             gui = np.asarray(ctrs["GRBM_GUI_ACTIVE"])
             keep = gui >= 0.25 * np.median(gui)
             cyc = gui[keep].mean() / 8.0
             rec["cycles_per_xcd"] = float(cyc)
+
+            def mean(ctr):
+                for c in (ctr, ctr + "_sum"):
+                    if c in ctrs and len(ctrs[c]) == len(gui):
+                        return float(np.asarray(ctrs[c])[keep].mean())
+                return None
+
             for ctr, field in (("SQ_INSTS_VALU", "valu_inst_per_cu_clk"),
-                               ("SQ_VALU_MFMA_BUSY_CYCLES", "mfma_busy_per_cu_clk")):
-                if ctr in ctrs and len(ctrs[ctr]) == len(gui):
-                    v = np.asarray(ctrs[ctr])[keep].mean()
-                    rec[field] = float(v / (cyc * 256.0))
-                    rec[ctr.lower()] = float(v)
-        out[key] = rec
+                               ("SQ_VALU_MFMA_BUSY_CYCLES", "mfma_busy_per_cu_clk"),
+                               ("TA_TA_BUSY", "ta_busy_per_cu_clk")):
+                v = mean(ctr)
+                if v is not None:
+                    rec[field] = v / (cyc * 256.0)
+                    rec[ctr.lower()] = v
+            # issue events: a dual issue puts two VALU instructions in one
+            # quad-cycle of a SIMD; 256 CUs x 4 SIMDs x cycles / 4 quad-cycles
+            ins, dual = mean("SQ_INSTS_VALU"), mean("SQ_ACTIVE_INST_VALU2")
+            if ins is not None and dual is not None:
+                rec["valu_dual_issued"] = dual
+                rec["valu_issue_frac"] = (ins - dual) / (cyc * 256.0)
+            for ctr in ("TA_BUFFER_READ_WAVEFRONTS", "TCP_TOTAL_CACHE_ACCESSES", "TCP_TCC_READ_REQ"):
+                v = mean(ctr)
+                if v is not None:
+                    rec[ctr.lower()] = v
+    for rec in out.values():
+        if "fetch_kib" in rec and "write_kib" in rec:
+            rec["traffic_bytes"] = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] +
+                                             rec["write_kib"] * rec["write_scale"])
     old = {}
     try:
         old = json.load(open(TRAFFIC))
