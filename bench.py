@@ -92,6 +92,12 @@ def valu_frac(key):
     return recorded(key, "valu_issue_frac")
 
 
+def ta_frac(key):
+    """Fraction of the dispatch's cycles the CUs' texture addressers (which
+    process every vector-memory address) were busy, or None."""
+    return recorded(key, "ta_busy_per_cu_clk")
+
+
 def mfma_frac(key):
     """Matrix-core busy cycles of a kernel over the same figure for the BF16
     matrix-core loop (which reaches the published BF16 rate), or None."""
@@ -170,12 +176,17 @@ def eam_force_bytes(n_atoms, n_entries):
     return 2 * 4 * n_entries + (2 * 24 + 16 + 12) * n_atoms
 
 
-def roofline_hbm(kernel, byt, ms, copy_gbs, traffic, valu):
+def roofline_hbm(kernel, byt, ms, copy_gbs, traffic, keys):
+    """HBM roofline of one launch (or one pair of passes) with the counter
+    fractions of its kernels (profile keys, in launch order)."""
     a = byt / (ms * 1e-3) / 1e9
+    one = len(keys) == 1
+    valu = [valu_frac(k) for k in keys]
+    ta = [ta_frac(k) for k in keys]
     return {"bound": "hbm", "kernel": kernel, "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": a / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": byt, "launch_ms": ms,
             "copy_GBs": copy_gbs, "frac_of_copy": a / copy_gbs if copy_gbs else None,
-            "valu_issue_frac": valu}
+            "valu_issue_frac": valu[0] if one else valu, "texture_addresser_busy_frac": ta[0] if one else ta}
 
 
 def mlp_force_flops(n_atoms, n_in, n_entries):
@@ -485,7 +496,7 @@ def main():
             "force_error_vs_fp64_oracle": "<= 1e-5 normwise and per atom (tests/test_gpu_fullsize.py)",
         },
         "roofline": roofline_hbm("k_lj32 (md_forces_lj)", byt, st["forces_ms"], copy_gbs,
-                                 recorded_traffic("k_lj32_lj_voids_1.23M"), valu_frac("k_lj32_lj_voids_1.23M")),
+                                 recorded_traffic("k_lj32_lj_voids_1.23M"), ("k_lj32_lj_voids_1.23M",)),
         "forces_ms_std": st["forces_ms_std"],
         "measured_peaks": peaks,
         "phases_ms_per_call_api": {k: v[0] for k, v in r["phases"].items()},
@@ -510,8 +521,7 @@ def main():
         leg.update({
             "list_entries": sim3.n_pairs, "forces_bytes": b3,
             "roofline": roofline_hbm("k_eam_rho + k_eam_force (md_forces_eam)", b3, leg["forces_ms"], copy_gbs,
-                                     recorded_pair("k_eam_rho_cu_4M", "k_eam_force_cu_4M"), None),
-            "valu_issue_frac": [valu_frac("k_eam_rho_cu_4M"), valu_frac("k_eam_force_cu_4M")],
+                                     recorded_pair("k_eam_rho_cu_4M", "k_eam_force_cu_4M"), ("k_eam_rho_cu_4M", "k_eam_force_cu_4M")),
             "phases_ms_per_call_api": {k: v[0] for k, v in r3["phases"].items()},
         })
         extra["eam_cu_fcc_100^3"] = leg
@@ -533,8 +543,7 @@ def main():
         leg.update({
             "list_entries": sim5.n_pairs, "forces_bytes": b5,
             "roofline": roofline_hbm("k_eam_rho<TB32> + k_eam_force<TB32> (md_forces_tb)", b5, leg["forces_ms"],
-                                     copy_gbs, recorded_pair("k_tb_rho_cu_4M", "k_tb_force_cu_4M"), None),
-            "valu_issue_frac": [valu_frac("k_tb_rho_cu_4M"), valu_frac("k_tb_force_cu_4M")],
+                                     copy_gbs, recorded_pair("k_tb_rho_cu_4M", "k_tb_force_cu_4M"), ("k_tb_rho_cu_4M", "k_tb_force_cu_4M")),
             "potential": "second-moment tight-binding (exponential psi and Phi, sqrt embedding), "
                          "synthetic Cu-like parameters, rc 5.0 A, list 6.0 A",
         })
@@ -553,8 +562,7 @@ def main():
         leg.update({
             "list_entries": sim7.n_pairs, "forces_bytes": b7,
             "roofline": roofline_hbm("k_tab_rho + k_tab_force (md_forces_tab)", b7, leg["forces_ms"], copy_gbs,
-                                     recorded_pair("k_tab_rho_cu_4M", "k_tab_force_cu_4M"), None),
-            "valu_issue_frac": [valu_frac("k_tab_rho_cu_4M"), valu_frac("k_tab_force_cu_4M")],
+                                     recorded_pair("k_tab_rho_cu_4M", "k_tab_force_cu_4M"), ("k_tab_rho_cu_4M", "k_tab_force_cu_4M")),
             "potential": "tabulated psi, Phi, F (cubic Hermite between knots) sampled from the FS set: "
                          f"{len(tab7['psi'])} r knots at 0.005 A, {len(tab7['F'])} rho knots; list 5.4 A",
         })
@@ -615,8 +623,7 @@ def main():
                 "list_entries": sim6.n_pairs, "fraction_element_1": s6.meta["frac_au"], "forces_bytes": b6,
                 "roofline": roofline_hbm("k_eam_rho<TBM32> + k_eam_force<TBM32> (md_forces_tbm)", b6,
                                          leg["forces_ms"], copy_gbs,
-                                         recorded_pair("k_tbm_rho_cu_au_4M", "k_tbm_force_cu_au_4M"), None),
-                "valu_issue_frac": [valu_frac("k_tbm_rho_cu_au_4M"), valu_frac("k_tbm_force_cu_au_4M")],
+                                         recorded_pair("k_tbm_rho_cu_au_4M", "k_tbm_force_cu_au_4M"), ("k_tbm_rho_cu_au_4M", "k_tbm_force_cu_au_4M")),
             })
             extra[name] = leg
             del sim6, s6
@@ -633,7 +640,7 @@ def main():
             "list_entries": sim4.n_pairs, "slab_atoms": s4.meta["slab_atoms"],
             "cluster_atoms": s4.meta["cluster_atoms"],
             "roofline": roofline_hbm("k_lj32 (md_forces_lj)", b4, leg["forces_ms"], copy_gbs,
-                                     recorded_traffic("k_lj32_lj_slab_32M"), valu_frac("k_lj32_lj_slab_32M")),
+                                     recorded_traffic("k_lj32_lj_slab_32M"), ("k_lj32_lj_slab_32M",)),
             "phases_ms_per_call_api": {k: v[0] for k, v in r4["phases"].items()},
         })
         extra["lj_slab_cluster_32M"] = leg
@@ -663,6 +670,7 @@ def main():
             "frac_of_measured_fma_loop": fl / (t_ms * 1e-3) / 1e12 / peaks["fp32_fma_TFLOPs"],
             "traffic": recorded_traffic("k_mlp_force_cu_4M"),
             "valu_issue_frac": valu_frac("k_mlp_force_cu_4M"),
+            "texture_addresser_busy_frac": ta_frac("k_mlp_force_cu_4M"),
             "net_mfma_frac_of_mfma_loop": mfma_frac("k_mlp_net_cu_4M"),
             "launch_ms": t_ms,
         }
