@@ -603,11 +603,14 @@ __device__ __forceinline__ int32_t nb_one_cell(NbWaveLds &L, int64_t rank, int64
                                : nb_cell<false>(L, n, x, g, rl2, keep2, nodup, h0, h1, m, carry, row_cap, idx, count);
 }
 
-__global__ __launch_bounds__(kNbBlock) void k_neighbors(int64_t n, const double *x, GridArgs g, double rl2,
-                                                        double keep2, int64_t n_cells, const int32_t *cell_start,
-                                                        const int32_t *rank_xyz, const int32_t *lin2rank,
-                                                        int32_t row_cap, int32_t *idx, int32_t *count,
-                                                        int32_t *max_count)
+// The per-wave LDS (about 6 KB) lets a CU hold 26 waves, 6 per SIMD; the
+// register budget is set to match (80 VGPRs instead of the 83 the compiler
+// would take, which allow only 5): the candidate gathers and the dependent
+// loads of the stencil set-up need the waves to hide their latency.
+__global__ __launch_bounds__(kNbBlock) __attribute__((amdgpu_waves_per_eu(6)))
+void k_neighbors(int64_t n, const double *x, GridArgs g, double rl2, double keep2, int64_t n_cells,
+                 const int32_t *cell_start, const int32_t *rank_xyz, const int32_t *lin2rank, int32_t row_cap,
+                 int32_t *idx, int32_t *count, int32_t *max_count)
 {
     __shared__ NbWaveLds lds_all[kNbWaves];
     const int lane = threadIdx.x % kWave, wave = uni(threadIdx.x / kWave);

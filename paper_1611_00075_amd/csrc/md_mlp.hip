@@ -445,10 +445,12 @@ __global__ __launch_bounds__(kBlock) void k_mlp_desc(int64_t n, MlpArgs p, const
 // Energies E_i (e_atom, may be NULL; FP64 block partial in part if not NULL)
 // and dE/dG (dEdG, may be NULL).  Gin and dEdG may be the same buffer: a
 // wavefront reads its 16 rows before it writes them.
+// Two waves per SIMD (at most 256 registers: the compiler would otherwise
+// keep every weight operand in registers and run one wave per SIMD).
 template <int NS>
-__global__ __launch_bounds__(kBlock) void k_mlp_net(int64_t n, MlpArgs p, const float *Gin,
-                                                    const uint16_t *__restrict__ w, float *__restrict__ e_atom,
-                                                    float *dEdG, double *__restrict__ part)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void k_mlp_net(int64_t n, MlpArgs p, const float *Gin, const uint16_t *__restrict__ w, float *__restrict__ e_atom,
+               float *dEdG, double *__restrict__ part)
 {
     if (gated(p.gate)) return;
     __shared__ WeightsLds L;
@@ -462,12 +464,22 @@ __global__ __launch_bounds__(kBlock) void k_mlp_net(int64_t n, MlpArgs p, const 
     const int64_t c0 = chunks * blk / gridDim.x, c1 = chunks * (blk + 1) / gridDim.x;
     double esum = 0.0;
 
+    // the next chunk's inputs are loaded while the current chunk computes
+    float4 n0 = {0.f, 0.f, 0.f, 0.f}, n1 = n0;
+    auto fetch = [&](int64_t c) {
+        const int64_t i = c * kChunk + int64_t(wave) * kTile + m;
+        if (g < 2 && i < n) {
+            n0 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g);
+            n1 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g + 4);
+        }
+    };
+    if (c0 < c1) fetch(c0);
     for (int64_t c = c0; c < c1; ++c) {
         const int64_t i = c * kChunk + int64_t(wave) * kTile + m;
+        const float4 u0 = n0, u1 = n1;
+        if (c + 1 < c1) fetch(c + 1);
         float u[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (g < 2 && i < n) {
-            const float4 u0 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g);
-            const float4 u1 = *reinterpret_cast<const float4 *>(Gin + i * kIn + 8 * g + 4);
             const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
 #pragma unroll
             for (int j = 0; j < 8; ++j) u[j] = (v[j] - L.mean[8 * g + j]) * L.inv_std[8 * g + j];
