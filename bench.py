@@ -439,11 +439,15 @@ def main():
     ap.add_argument("--mlp-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=3, help="single-thread oracle steps")
     ap.add_argument("--cpu-all-steps", type=int, default=20, help="all-core oracle steps")
+    ap.add_argument("--trace-summary", help="rocprofv3 --kernel-trace output directory: print a per-kernel table")
     ap.add_argument("--counters", default=None,
                     help="comma-separated rocprofv3 --pmc output directories: write profiles/traffic.json")
     args = ap.parse_args()
     if args.counters:
         summarize_counters(args.counters.split(","))
+        return
+    if args.trace_summary:
+        summarize_trace(args.trace_summary)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark measures one GPU; --gpus must be 1"}))
@@ -739,6 +743,27 @@ def _read_counters(dirs):
             for (disp, name, grid, ctr), v in per.items():
                 out.setdefault((name, grid), {}).setdefault(ctr, []).append(v)
     return out
+
+
+def summarize_trace(d):
+    """Per (kernel, grid) table of a rocprofv3 --kernel-trace output
+    directory: launches, mean and median duration, and the mean over the
+    full launches (those above a quarter of the median; the force kernels'
+    skipped speculative launches fall below it)."""
+    import csv
+    import glob
+    rows = {}
+    for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            rows.setdefault((r["Kernel_Name"], g), []).append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0)
+    print("kernel\tgrid\tlaunches\tmean_us\tmedian_us\tfull_launches\tfull_mean_us\ttotal_ms")
+    for (name, g), v in sorted(rows.items(), key=lambda kv: -sum(kv[1])):
+        v = np.asarray(v)
+        full = v[v >= 0.25 * np.median(v)]
+        print(f"{name[:120]}\t{g}\t{len(v)}\t{v.mean():.2f}\t{np.median(v):.2f}\t{len(full)}\t"
+              f"{full.mean():.2f}\t{v.sum() / 1e3:.3f}")
 
 
 def summarize_counters(dirs):
