@@ -119,3 +119,25 @@ def test_size_limits_rejected_before_any_device_work(lib):
                                        C.POINTER(C.c_int32), vp, C.c_size_t, vp]
     assert lib.md_build_neighbors(C.byref(g), 0, None, vp(8), md.MD_MAX_ROW_CAP + 8, None, None, vp(8), None,
                                   None, 0, None) == md.MD_ERR_ARG
+
+
+def test_probe_and_noalloc_reject_bad_arguments(lib):
+    """The measurement probe and the allocation-free LJ entry point check
+    their arguments before any device work (NULL buffers; no GPU needed)."""
+    from paper_1611_00075_amd import md
+    vp = C.c_void_p
+    lib.md_probe.argtypes = [C.c_int32, C.c_int64, C.c_int32, vp, vp]
+    out = vp(8)
+    assert lib.md_probe(99, 1, 1, out, None) == md.MD_ERR_ARG            # unknown kind
+    assert lib.md_probe(md.MD_PROBE_FMA_F32, 0, 1, out, None) == md.MD_ERR_ARG
+    assert lib.md_probe(md.MD_PROBE_FMA_F32, 1, 0, out, None) == md.MD_ERR_ARG
+    assert lib.md_probe(md.MD_PROBE_MFMA_BF16, 1, 1, None, None) == md.MD_ERR_ARG
+    box = md.Box((C.c_double * 3)(20.0, 20.0, 20.0))
+    lj = md.LJ(1.0, 1.0, 2.5)
+    lib.md_forces_lj_noalloc.argtypes = [C.POINTER(md.Box), C.c_int64, vp, vp, C.c_int32, vp, vp,
+                                         C.POINTER(md.LJ), vp, vp, C.c_int32, vp]
+    big = md.MD_MAX_ATOMS_FP32 + 1
+    assert lib.md_forces_lj_noalloc(C.byref(box), big, None, None, 64, None, None, C.byref(lj), None, None, 0,
+                                    None) == md.MD_ERR_ARG
+    assert lib.md_forces_lj_noalloc(C.byref(box), 10, None, None, 64, None, None, C.byref(lj), None, None, 0,
+                                    None) == md.MD_ERR_ARG                # NULL buffers
