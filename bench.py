@@ -440,6 +440,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3, help="single-thread oracle steps")
     ap.add_argument("--cpu-all-steps", type=int, default=20, help="all-core oracle steps")
     ap.add_argument("--trace-summary", help="rocprofv3 --kernel-trace output directory: print a per-kernel table")
+    ap.add_argument("--dd-overlap", help="rocprofv3 --kernel-trace output directory of decomposed force "
+                                         "evaluations: print the halo/compute overlap")
     ap.add_argument("--counters", default=None,
                     help="comma-separated rocprofv3 --pmc output directories: write profiles/traffic.json")
     args = ap.parse_args()
@@ -448,6 +450,9 @@ def main():
         return
     if args.trace_summary:
         summarize_trace(args.trace_summary)
+        return
+    if args.dd_overlap:
+        summarize_dd_overlap(args.dd_overlap)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark measures one GPU; --gpus must be 1"}))
@@ -764,6 +769,58 @@ def summarize_trace(d):
         full = v[v >= 0.25 * np.median(v)]
         print(f"{name[:120]}\t{g}\t{len(v)}\t{v.mean():.2f}\t{np.median(v):.2f}\t{len(full)}\t"
               f"{full.mean():.2f}\t{v.sum() / 1e3:.3f}")
+
+
+def summarize_dd_overlap(d):
+    """Halo exchange against compute per force evaluation of a decomposed
+    system, from a rocprofv3 --kernel-trace of repeated
+    DomainSimulation.compute_forces calls: for each evaluation (it starts
+    with k_dd_scale_local) the span, the inner and outer launches of the two
+    passes (the inner one has the larger grid), and the position and F'
+    halos from the start of their pack to the end of their unpack, with
+    whether each ends inside the inner launch it overlaps.  Prints means,
+    minima and maxima over the evaluations after the first two."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            m = re.search(r"(k_\w+?)(<[^()]*>)?\(", r["Kernel_Name"])   # the kernel's own name
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), m.group(1) if m else r["Kernel_Name"],
+                         int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])))
+    rows.sort()
+    evals = []
+    for t0, t1, name, grid in rows:
+        if name == "k_dd_scale_local":
+            evals.append({"t0": t0, "k": []})
+        if evals:
+            evals[-1]["k"].append((t0, t1, name, grid))
+    res = []
+    for e in evals:
+        ks = e["k"]
+
+        def pick(kernel):
+            return [k for k in ks if k[2] == kernel]
+
+        rho = sorted(pick("k_eam_rho")[:2], key=lambda k: -k[3])
+        frc = sorted(pick("k_eam_force")[:2], key=lambda k: -k[3])
+        pk, up, pkw, upw = pick("k_dd_pack"), pick("k_dd_unpack"), pick("k_dd_pack_w"), pick("k_dd_unpack_w")
+        if len(rho) < 2 or len(frc) < 2 or not (pk and up and pkw and upw):
+            continue
+        end = max(k[1] for k in ks if "k_eam" in k[2] or "k_dd" in k[2])
+        us = 1e-3
+        res.append({"span_us": (end - e["t0"]) * us,
+                    "rho_inner_us": (rho[0][1] - rho[0][0]) * us, "rho_outer_us": (rho[1][1] - rho[1][0]) * us,
+                    "force_inner_us": (frc[0][1] - frc[0][0]) * us, "force_outer_us": (frc[1][1] - frc[1][0]) * us,
+                    "position_halo_us": (up[0][1] - pk[0][0]) * us,
+                    "position_halo_inside": float(up[0][1] <= rho[0][1]),
+                    "fprime_halo_us": (upw[0][1] - pkw[0][0]) * us,
+                    "fprime_halo_inside": float(upw[0][1] <= frc[0][1])})
+    tail = res[2:]
+    print(f"evaluations: {len(res)} of {len(evals)}; statistics over the {len(tail)} after the first two")
+    for k in (tail[0] if tail else {}):
+        v = np.array([r[k] for r in tail])
+        print(f"{k}\tmean {v.mean():.2f}\tmin {v.min():.2f}\tmax {v.max():.2f}")
 
 
 def summarize_counters(dirs):

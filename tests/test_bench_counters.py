@@ -106,3 +106,35 @@ def test_trace_summary_drops_skipped_launches(tmp_path, capsys):
     assert int(f[1]) == GRID and int(f[2]) == 4
     assert float(f[3]) == pytest.approx((120 + 124 + 8 + 122) / 4, abs=0.01)
     assert int(f[5]) == 3 and float(f[6]) == pytest.approx(122.0, abs=0.01)
+
+
+def test_dd_overlap_summary(tmp_path, capsys):
+    """Two synthetic evaluations after two set-up ones: the halos' spans, the
+    inner launches (larger grid) and whether each halo ends inside them."""
+    d = tmp_path / "dd" / "host"
+    d.mkdir(parents=True)
+    ns = "md::(anonymous namespace)::"
+    rows = []
+    for e in range(4):
+        b = e * 10_000_000
+        rows += [(ns + "k_dd_scale_local(long, double const*)", 4000000, b, b + 38000),
+                 (ns + "k_dd_pack(long, double const*, long)", 900352, b + 40000, b + 62000),
+                 (ns + "k_dd_unpack(long, double const*)", 900352, b + 120000, b + 141000),
+                 ("void md::k_eam_rho<md::FS32, 8, 4, true, false, true>(long)", 25739264, b + 39000, b + 317000),
+                 ("void md::k_eam_rho<md::FS32, 8, 4, true, false, true>(long)", 6260736, b + 318000, b + 386000),
+                 (ns + "k_dd_pack_w(long, HIP_vector_type<unsigned int, 4u>)", 900352, b + 387000, b + 404000),
+                 (ns + "k_dd_unpack_w(long, unsigned int)", 900352, b + 480000, b + 697000),
+                 ("void md::k_eam_force<md::FS32, 8, 4, true, false, true>(long)", 25739264, b + 387000, b + 676000),
+                 ("void md::k_eam_force<md::FS32, 8, 4, true, false, true>(long)", 6260736, b + 677000, b + 751000)]
+    with open(d / "1_kernel_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z", "Start_Timestamp", "End_Timestamp"])
+        for name, g, a, z in rows:
+            w.writerow([name, g, 1, 1, a, z])
+    bench.summarize_dd_overlap(str(tmp_path / "dd"))
+    out = dict(line.split("\t")[:2] for line in capsys.readouterr().out.strip().splitlines()[1:])
+    assert out["span_us"] == "mean 751.00"
+    assert out["rho_inner_us"] == "mean 278.00" and out["rho_outer_us"] == "mean 68.00"
+    assert out["position_halo_us"] == "mean 101.00" and out["position_halo_inside"] == "mean 1.00"
+    # this F' halo ends after the inner force launch
+    assert out["fprime_halo_us"] == "mean 310.00" and out["fprime_halo_inside"] == "mean 0.00"
