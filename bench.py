@@ -440,6 +440,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3, help="single-thread oracle steps")
     ap.add_argument("--cpu-all-steps", type=int, default=20, help="all-core oracle steps")
     ap.add_argument("--trace-summary", help="rocprofv3 --kernel-trace output directory: print a per-kernel table")
+    ap.add_argument("--nb-candidates", choices=["voids", "cu54"],
+                    help="CPU model of the neighbour build's candidate counts on a benchmark system")
     ap.add_argument("--dd-overlap", help="rocprofv3 --kernel-trace output directory of decomposed force "
                                          "evaluations: print the halo/compute overlap")
     ap.add_argument("--counters", default=None,
@@ -453,6 +455,9 @@ def main():
         return
     if args.dd_overlap:
         summarize_dd_overlap(args.dd_overlap)
+        return
+    if args.nb_candidates:
+        neighbor_candidates(args.nb_candidates)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark measures one GPU; --gpus must be 1"}))
@@ -821,6 +826,54 @@ def summarize_dd_overlap(d):
     for k in (tail[0] if tail else {}):
         v = np.array([r[k] for r in tail])
         print(f"{k}\tmean {v.mean():.2f}\tmin {v.min():.2f}\tmax {v.max():.2f}")
+
+
+def neighbor_candidates(which, samples=3000, seed=0):
+    """CPU model of the neighbour build's candidate selection on a system's
+    initial configuration: for a sample of occupied cells (edge >= r_list,
+    27-cell stencil), the candidates each home atom's wave streams (all atoms
+    of the stencil), those within r_list of the bounding box of the cell's
+    home atoms (kept and tested exactly, in 64-candidate chunks), and the
+    home atom's list entries.  Prints one JSON line."""
+    from paper_1611_00075_amd import inputs
+    s, rl = (inputs.lj_voids(), 2.8) if which == "voids" else (inputs.eam_cu(), 5.4)
+    L = float(s.L[0])
+    x = np.mod(s.x, L)
+    nc = int(np.floor(L / rl))
+    c = np.minimum((x * (nc / L)).astype(np.int64), nc - 1)
+    lin = c[:, 0] + nc * (c[:, 1] + nc * c[:, 2])
+    order = np.argsort(lin, kind="stable")
+    xs, ls = x[order], lin[order]
+    start = np.concatenate([[0], np.cumsum(np.bincount(ls, minlength=nc ** 3))])
+    occupied = np.nonzero(np.diff(start))[0]
+    cells = np.random.default_rng(seed).choice(occupied, min(samples, len(occupied)), replace=False)
+    homes = streamed = kept = chunks = hits = 0
+    for cl in cells:
+        cz, rem = divmod(int(cl), nc * nc)
+        cy, cx = divmod(rem, nc)
+        h = xs[start[cl]:start[cl + 1]]
+        cand = []
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    k = np.array([cx + dx, cy + dy, cz + dz])
+                    img, k = np.floor_divide(k, nc), np.mod(k, nc)
+                    q = k[0] + nc * (k[1] + nc * k[2])
+                    cand.append(xs[start[q]:start[q + 1]] + img * L)
+        cand = np.concatenate(cand)
+        lo, hi = h.min(0), h.max(0)
+        d = np.maximum(np.maximum(lo - cand, cand - hi), 0.0)
+        kc = cand[(d * d).sum(1) < rl * rl]
+        r2 = ((h[:, None, :] - kc[None, :, :]) ** 2).sum(2)
+        homes += len(h)
+        streamed += len(cand) * len(h)
+        kept += len(kc) * len(h)
+        chunks += -(-len(kc) // 64) * len(h)
+        hits += int((r2 < rl * rl).sum()) - len(h)        # less each home itself
+    print(json.dumps({"system": which, "r_list": rl, "cells_sampled": int(len(cells)), "home_atoms": homes,
+                      "streamed_per_home": streamed / homes, "kept_per_home": kept / homes,
+                      "chunks_per_home": chunks / homes, "entries_per_home": hits / homes,
+                      "tested_per_entry": 64.0 * chunks / hits, "streamed_per_entry": streamed / hits}))
 
 
 def summarize_counters(dirs):

@@ -138,3 +138,16 @@ def test_dd_overlap_summary(tmp_path, capsys):
     assert out["position_halo_us"] == "mean 101.00" and out["position_halo_inside"] == "mean 1.00"
     # this F' halo ends after the inner force launch
     assert out["fprime_halo_us"] == "mean 310.00" and out["fprime_halo_inside"] == "mean 0.00"
+
+
+def test_neighbor_candidate_model(capsys):
+    """The candidate model on the perfect Cu crystal (plus its thermal start):
+    every home atom has the 54 fcc neighbours within 5.4 A (shells of 12, 6,
+    24 and 12), and the bounding-box test keeps a subset of what is streamed
+    and all of what is listed."""
+    bench.neighbor_candidates("cu54", samples=200)
+    r = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert r["entries_per_home"] == pytest.approx(54.0)
+    assert r["entries_per_home"] <= r["kept_per_home"] <= r["streamed_per_home"]
+    assert r["chunks_per_home"] * 64 >= r["kept_per_home"]
+    assert r["tested_per_entry"] > 1.0
