@@ -348,7 +348,6 @@ template <int NC, bool INTERIOR>
 __device__ __forceinline__ uint32_t nb_home(const NbTile &T, double xi, double yi, double zi, int32_t i, uint32_t r,
                                             __amdgpu_buffer_rsrc_t row, double rl2, const GridArgs &g)
 {
-    bool hit[NC];
     uint64_t mk[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -359,8 +358,9 @@ __device__ __forceinline__ uint32_t nb_home(const NbTile &T, double xi, double y
             dz = minimg_sel(dz, g.L[2], g.hL[2]);
         }
         const double r2 = (dx * dx + dy * dy) + dz * dz;
-        hit[c] = (T.j[c] != i) && (r2 < rl2);
-        mk[c] = __builtin_amdgcn_ballot_w64(hit[c]);
+        // the wave's hit mask straight from the two compares (r2 < rl2 as an
+        // ordered less-than, so a +inf padding candidate never hits)
+        mk[c] = __builtin_amdgcn_fcmp(r2, rl2, 4) & __builtin_amdgcn_ballot_w64(T.j[c] != i);
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -368,7 +368,8 @@ __device__ __forceinline__ uint32_t nb_home(const NbTile &T, double xi, double y
         const uint32_t e = __builtin_amdgcn_mbcnt_hi(uint32_t(mk[c] >> 32),
                                                      __builtin_amdgcn_mbcnt_lo(uint32_t(mk[c]), r));
         // entry e of the row at byte (e / 8) * 256 + (e % 8) * 4
-        if (hit[c]) __builtin_amdgcn_raw_buffer_store_b32(T.j[c], row, (e << 2) + __umul24(e >> 3, 224u), 0, 0);
+        if (__builtin_amdgcn_inverse_ballot_w64(mk[c]))   // this lane's bit of the mask
+            __builtin_amdgcn_raw_buffer_store_b32(T.j[c], row, (e << 2) + __umul24(e >> 3, 224u), 0, 0);
         r += uint32_t(__popcll(mk[c]));
     }
     return r;
