@@ -364,10 +364,12 @@ __device__ __forceinline__ int32_t descriptor(const MlpArgs &p, const uint4 *__r
             float dx, dy, dz;
             disp<false>(pi, pj[u], p.ax, p.ay, p.az, dx, dy, dz);
             const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-            const bool in = t0 + u * kSlice + sub < cnt && r2 < p.rc2;
-            const uint32_t gm = uint32_t(__ballot(in) >> (lane & ~(kSlice - 1))) & 0xffu;
+            // the wave's mask of pairs within rc, straight from the compares
+            const uint64_t inm = __builtin_amdgcn_ballot_w64(t0 + u * kSlice + sub < cnt) &
+                                 __builtin_amdgcn_fcmpf(r2, p.rc2, 4);   // ordered less-than
+            const uint32_t gm = uint32_t(inm >> (lane & ~(kSlice - 1))) & 0xffu;
             const int32_t pos = base + __popc(gm & ((1u << sub) - 1u));
-            if (in) {
+            if (__builtin_amdgcn_inverse_ballot_w64(inm)) {
                 seg[pos] = __builtin_amdgcn_sqrtf(r2);
                 if (orow) orow[ell_pos(pos)] = j[u];
             }
