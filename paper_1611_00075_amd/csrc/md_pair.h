@@ -128,9 +128,11 @@ __device__ __forceinline__ void walk_buf(const __amdgpu_buffer_rsrc_t &xs_r, con
 // U - 1 slots, body(pj, t, Masked<true>) with pj of length U - 1; the loads
 // of slots past the end are switched off in the execution mask (zeros in
 // pj).  A lane given an out-of-range offset instead still passes through
-// the gather's address processing, the kernels' limit: masking took the LJ
-// kernel from 0.130 to 0.1255 ms.  A lane thus evaluates fewer slots than
-// U * ceil(cnt / 8U) and makes no selects in its full batches.
+// the gather's address processing and issue: masking took the LJ kernel
+// from 0.130 to 0.1255 ms.  A lane thus evaluates fewer slots than
+// U * ceil(cnt / 8U) and makes no selects in its full batches.  (What
+// bounds the pair kernels is the list stream, 4 bytes per entry read once,
+// together with the pair arithmetic; the position gathers add little.)
 template <int U, int WORDS, typename Body>
 __device__ __forceinline__ void walk_split(const __amdgpu_buffer_rsrc_t &xs_r, const __amdgpu_buffer_rsrc_t &row_r,
                                            int32_t cnt, int sub, Body &&body)
